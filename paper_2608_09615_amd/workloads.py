@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module generates states only; it holds none of the SD method's
+arithmetic, so that both the oracle side and the HIP side can be fed from it.
+Point coordinates come from numpy's Gauss-Legendre rule.
+
+Layouts: 1-D states are ``[N, n]``; 3-D states are ``[ne, nv, n, n, n]``
+indexed ``[e, v, k, j, i]`` with ``e = ex + Nx*(ey + Ny*ez)`` and ``i``
+along x; ``n = p + 1``.
+"""
+import math
+
+import numpy as np
+
+
+def gl_nodes(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return x, w
+
+
+def points_1d(N, p, x0, x1):
+    """Physical solution-point coordinates, shape [N, p+1]."""
+    xs, _ = gl_nodes(p + 1)
+    h = (x1 - x0) / N
+    left = x0 + h * np.arange(N)
+    return left[:, None] + 0.5 * h * (xs[None, :] + 1.0)
+
+
+def sine_1d(N, p, x0, x1, k=1.0, phase=0.0):
+    return np.sin(k * points_1d(N, p, x0, x1) + phase)
+
+
+def dirac_1d(N, p, x0, x1, seed=0):
+    """Discrete delta of unit integral: 1/h on every point of one element
+    chosen by the seeded generator (PCG64)."""
+    e = int(np.random.Generator(np.random.PCG64(seed)).integers(N))
+    u = np.zeros((N, p + 1))
+    u[e, :] = N / (x1 - x0)
+    return u, e
+
+
+def barenblatt(x, t, m, C=0.1):
+    """Zeldovich-Kompaneets-Barenblatt profile in one dimension (d = 1)."""
+    alpha = 1.0 / ((m - 1.0) + 2.0)
+    beta = alpha
+    arg = C - alpha * (m - 1.0) / (2.0 * m) * x * x * t ** (-2.0 * beta)
+    return t ** (-alpha) * np.maximum(arg, 0.0) ** (1.0 / (m - 1.0))
+
+
+def barenblatt_t0(m, dx, C=0.1):
+    """Start time at which the support half-width equals dx/2."""
+    a1 = 1.0 / ((m - 1.0) + 2.0)
+    return (C * 2.0 * m / (a1 * (m - 1.0)) * (2.0 / dx) ** 2) ** (-1.0 / (2.0 * a1))
+
+
+def barenblatt_H(m, t, C=0.1):
+    a1 = 1.0 / ((m - 1.0) + 2.0)
+    return 2.0 * m * C / (a1 * (m - 1.0)) * t ** (2.0 * a1)
+
+
+def points_3d(nel, lo, hi, p):
+    """Coordinates X, Y, Z of shape [ne, n, n, n] (axes k, j, i)."""
+    n = p + 1
+    xs, _ = gl_nodes(n)
+    out = []
+    for d in range(3):
+        h = (hi[d] - lo[d]) / nel[d]
+        out.append(lo[d] + h * np.arange(nel[d])[:, None] + 0.5 * h * (xs[None, :] + 1.0))
+    X1, Y1, Z1 = out
+    ne = nel[0] * nel[1] * nel[2]
+    ex = np.arange(ne) % nel[0]
+    ey = (np.arange(ne) // nel[0]) % nel[1]
+    ez = np.arange(ne) // (nel[0] * nel[1])
+    X = np.broadcast_to(X1[ex][:, None, None, :], (ne, n, n, n))
+    Y = np.broadcast_to(Y1[ey][:, None, :, None], (ne, n, n, n))
+    Z = np.broadcast_to(Z1[ez][:, :, None, None], (ne, n, n, n))
+    return X, Y, Z
+
+
+def tgv_primitive(X, Y, Z, Ma=0.1, gamma=1.4, rho0=1.0, u0=1.0, L=1.0, phase=(0.0, 0.0, 0.0)):
+    """Taylor-Green vortex on [0, 2 pi L]^3 with x* = (x - x_c)/L."""
+    xc = math.pi * L
+    xs = (X - xc) / L + phase[0]
+    ys = (Y - xc) / L + phase[1]
+    zs = (Z - xc) / L + phase[2]
+    p0 = rho0 / gamma * (u0 / Ma) ** 2
+    rho = np.full(X.shape, rho0)
+    u = u0 * np.sin(xs) * np.cos(ys) * np.cos(zs)
+    v = -u0 * np.cos(xs) * np.sin(ys) * np.cos(zs)
+    w = np.zeros(X.shape)
+    pr = p0 + rho0 * u0 ** 2 / 16.0 * np.cos(2 * xs) * np.cos(2 * ys) * (np.cos(2 * zs) + 2.0)
+    return rho, u, v, w, pr
+
+
+def conservative(rho, u, v, w, pr, gamma=1.4):
+    rhoE = pr / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, rhoE], axis=1)
+
+
+def tgv_state(nel, p, Ma=0.1, gamma=1.4, rho0=1.0, u0=1.0, L=1.0, phase=(0.0, 0.0, 0.0)):
+    """Conservative TGV state [ne, 5, n, n, n] on the periodic box [0, 2 pi L]^3."""
+    lo = (0.0, 0.0, 0.0)
+    hi = (2 * math.pi * L,) * 3
+    X, Y, Z = points_3d(nel, lo, hi, p)
+    prim = tgv_primitive(X, Y, Z, Ma, gamma, rho0, u0, L, phase)
+    return conservative(*prim, gamma=gamma)
+
+
+def tgv_domain(L=1.0):
+    return (0.0, 0.0, 0.0), (2 * math.pi * L,) * 3
+
+
+def perturbed_tgv_state(nel, p, seed, amp=1e-2, Ma=0.1, gamma=1.4, noise=0.0, kmax=4):
+    """TGV with a seeded random phase shift and a random-phase solenoidal
+    velocity perturbation of wavenumbers |k|_inf <= kmax; ``noise`` adds
+    pointwise seeded noise (relative to each variable's scale) that breaks
+    every symmetry of the flow."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    phase = tuple(rng.uniform(0.0, 2 * math.pi, 3))
+    lo, hi = tgv_domain()
+    X, Y, Z = points_3d(nel, lo, hi, p)
+    rho, u, v, w, pr = tgv_primitive(X, Y, Z, Ma, gamma, phase=phase)
+    du = np.zeros((3,) + X.shape)
+    if amp > 0:
+        modes = []
+        for kx in range(-kmax, kmax + 1):
+            for ky in range(-kmax, kmax + 1):
+                for kz in range(-kmax, kmax + 1):
+                    if (kx, ky, kz) != (0, 0, 0):
+                        modes.append((kx, ky, kz))
+        for k in modes:
+            kv = np.array(k, dtype=float)
+            a = rng.normal(size=3)
+            a -= kv * (a @ kv) / (kv @ kv)          # solenoidal: a . k = 0
+            ph = rng.uniform(0, 2 * math.pi)
+            arg = kv[0] * X + kv[1] * Y + kv[2] * Z + ph
+            s = np.cos(arg) / (kv @ kv)
+            for c in range(3):
+                du[c] += a[c] * s
+        du *= amp / max(np.abs(du).max(), 1e-300)
+    U = conservative(rho, u + du[0], v + du[1], w + du[2], pr, gamma)
+    if noise > 0:
+        scale = np.array([1.0, 1.0, 1.0, 1.0, 1.0])
+        U = U + noise * scale[None, :, None, None, None] * rng.uniform(-1, 1, U.shape)
+    return U
+
+
+def sine_3d(nel, lo, hi, p, k=(1, 1, 1)):
+    X, Y, Z = points_3d(nel, lo, hi, p)
+    return (np.sin(k[0] * X) * np.sin(k[1] * Y) * np.sin(k[2] * Z))[:, None]
+
+
+def random_scalar_3d(nel, p, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ne = nel[0] * nel[1] * nel[2]
+    return rng.uniform(-1, 1, (ne, 1, p + 1, p + 1, p + 1))
