@@ -1,0 +1,143 @@
+/*
+ * sd.h - C ABI of the MI355X Spectral Difference right-hand side.
+ *
+ * The library evaluates the semi-discrete SD right-hand side of
+ *     du/dt + div F(u, grad u) = 0,
+ * written as the first-order system with the auxiliary gradient v = grad u
+ * and mapped to the reference hexahedron (Lodato & Tonicello, section 2,
+ * eqs. ns and ns:mapped/adj:f), on uniform periodic Cartesian meshes.  The
+ * auxiliary gradient is reconstructed either with the standard BR1-type
+ * centred treatment (section 2.1: common solution eq. c:flux, gradient
+ * eqs. w:e/v:e, common gradient eq. aux:v:int; five-element stencil in 1-D)
+ * or with the compact one-sided continuous fluxes (section 2.2: eqs.
+ * c:flux:l/r, v:s:l/r, cmp:int:fp, cmp:int:avg; three-element stencil), and
+ * in three dimensions with the direction-by-direction construction of
+ * section 2.3.  Interface viscous fluxes use option (a) of section 2.1
+ * (flux of the averaged solution and averaged gradient).  Physics: linear
+ * diffusion, the porous medium equation (section 4.3) and the compressible
+ * Navier-Stokes equations of section 4.4 (Roe flux with Harten's entropy fix
+ * at interfaces, Sutherland viscosity, gradients of conservative
+ * variables).
+ *
+ * Points: n = p + 1 Gauss-Legendre solution points per direction; n + 1 flux
+ * points (the two element ends and the (n-1)-point Gauss-Legendre rule).
+ *
+ * State layout (device memory, FP64, owned by the caller):
+ *   dim = 3: u[e][v][k][j][i], e = ex + Nx*(ey + Ny*ez), i along x fastest;
+ *   dim = 1: u[e][v][i].
+ *   nv = 1 for scalar physics, 5 for Navier-Stokes (rho, rho u, rho v,
+ *   rho w, rho E).
+ *
+ * Streams: every call is enqueued asynchronously on the context's HIP stream
+ * (the one given to sd_init or sd_set_stream); only sd_diagnostics waits for
+ * that stream, to fill its host-side result.
+ *
+ * Errors: every entry point returns SD_OK (0) or a negative code, and sets a
+ * thread-local message readable with sd_last_error().  On error nothing has
+ * been enqueued, except for SD_EHIP, where a launch may have failed midway.
+ */
+#ifndef SD_H
+#define SD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SD_OK 0
+#define SD_EINVAL (-1)       /* bad argument: null pointer, size, enum      */
+#define SD_ENOMEM (-2)       /* device or host allocation failed            */
+#define SD_EHIP (-3)         /* a HIP runtime call or kernel launch failed  */
+#define SD_ENONFINITE (-4)   /* diagnostics found a NaN or an infinity      */
+#define SD_EUNSUPPORTED (-5) /* valid but not built: p, dim x physics combo */
+
+typedef enum { SD_BR1 = 0, SD_COMPACT = 1 } sd_scheme;
+typedef enum { SD_DIFFUSION = 0, SD_PME = 1, SD_NAVIER_STOKES = 2 } sd_physics;
+/* Arithmetic of the contractions and fluxes.  The public state, the RHS and
+ * the RK accumulation stay FP64 in every mode. */
+typedef enum { SD_FP64 = 0, SD_FP32 = 1, SD_BF16X3 = 2 } sd_precision;
+
+/* Uniform periodic Cartesian mesh: dim 1 uses nelem[0], lo[0], hi[0] only. */
+typedef struct {
+  int dim;
+  int nelem[3];
+  double lo[3];
+  double hi[3];
+} sd_mesh;
+
+typedef struct {
+  int physics;            /* sd_physics                                      */
+  double nu;              /* diffusion coefficient                           */
+  double pme_m;           /* porous-medium exponent m, integer in [1, 8]     */
+  double gamma;           /* heat-capacity ratio (section 4.4: 1.4)          */
+  double Re, Ma, Pr;      /* mu0 = rho0 u0 L / Re, p0 = rho0 (u0/Ma)^2 / gamma */
+  double rho0, u0, Lref;  /* reference density, velocity and length         */
+  double sutherland_s;    /* Sutherland constant over the reference
+                             temperature p0/(rho0 R); negative: constant mu */
+  double lambda_over_mu;  /* second viscosity coefficient (section 4.4: 0)   */
+  double entropy_fix;     /* Harten delta = entropy_fix * (|u_n| + c), applied
+                             to the two acoustic waves; 0 disables it        */
+  int precision;          /* sd_precision                                    */
+  int ref_state;          /* 1: subtract the constant state (rho0, 0, 0, 0,
+                             p0/(gamma-1)) before the contractions (exact
+                             algebra: L reproduces constants, M annihilates
+                             them); -1: automatic (on unless FP64)          */
+} sd_params;
+
+typedef struct {
+  double ke;         /* 1/2 int u.u dV (section 4.4), Gauss quadrature      */
+  double enstrophy;  /* int w.w dV, w = curl u from the standard gradient   */
+  double mass;       /* int rho dV                                          */
+  double mom[3];     /* int rho u dV                                        */
+  double energy;     /* int rho E dV                                        */
+  double umax;       /* max |u| over the solution points                    */
+  int nonfinite;     /* 1 if any state value is NaN or infinite             */
+} sd_diag;
+
+typedef struct sd_ctx sd_ctx;
+
+/* Fill *prm with the Taylor-Green defaults (Navier-Stokes, gamma 1.4,
+ * Re 1600, Ma 0.1, Pr 0.71, rho0 = u0 = L = 1, Sutherland 110.4/300,
+ * lambda 0, entropy fix 0.1, FP64, automatic reference state). */
+int sd_params_default(sd_params *prm);
+
+/* Create a context for polynomial degree p (n = p + 1 points) and scheme
+ * (sd_scheme).  Supported: dim 1 with diffusion or PME, p in [1, 8]; dim 3
+ * with diffusion or Navier-Stokes, p in [1, 6] (FP64) or [1, 6] (FP32).
+ * stream: a hipStream_t (NULL = the default stream).  Allocates the
+ * operators and the scratch buffers (face traces, RK registers) on the
+ * current device; the context owns them until sd_free. */
+int sd_init(const sd_mesh *mesh, int p, int scheme, const sd_params *prm,
+            void *stream, sd_ctx **out);
+
+/* Release every resource of the context (waits for its stream). NULL is ok. */
+int sd_free(sd_ctx *ctx);
+
+/* Change the stream later calls are enqueued on. */
+int sd_set_stream(sd_ctx *ctx, void *stream);
+
+/* Number of FP64 values of one state: ne * nv * n^dim. */
+long long sd_state_size(const sd_ctx *ctx);
+
+/* dudt = R(u): the semi-discrete right-hand side at the solution points.
+ * u and dudt are device pointers of sd_state_size() doubles each and must
+ * not overlap.  u is read only. */
+int sd_rhs(sd_ctx *ctx, const double *u, double *dudt);
+
+/* One classical fourth-order Runge-Kutta step of size dt, in place on the
+ * device state u; stage states and the accumulation are FP64. */
+int sd_rk_step(sd_ctx *ctx, double *u, double dt);
+
+/* Diagnostics of a Navier-Stokes state (FP64 reductions, deterministic):
+ * waits for the stream and fills the host struct *out.  Returns
+ * SD_ENONFINITE (with *out filled) when the state holds NaN or Inf. */
+int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
+
+/* Message of the last error on this thread ("" if none). */
+const char *sd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SD_H */

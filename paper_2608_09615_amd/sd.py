@@ -1,0 +1,186 @@
+"""ctypes binding of ``libsd.so`` (argument marshalling only).
+
+Every step of the right-hand side runs in the library's HIP kernels; torch is
+used for device memory and the current stream.  If the library is missing the
+binding raises: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsd.so")
+
+SD_OK, SD_EINVAL, SD_ENOMEM, SD_EHIP, SD_ENONFINITE, SD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SCHEMES = {"br1": 0, "compact": 1}
+PHYSICS = {"diffusion": 0, "pme": 1, "ns": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
+           "sd_rk_step", "sd_diagnostics", "sd_last_error"]
+
+
+class SDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsd error {code}: {msg}")
+        self.code = code
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nelem", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("physics", ctypes.c_int),
+        ("nu", ctypes.c_double),
+        ("pme_m", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("Re", ctypes.c_double),
+        ("Ma", ctypes.c_double),
+        ("Pr", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("u0", ctypes.c_double),
+        ("Lref", ctypes.c_double),
+        ("sutherland_s", ctypes.c_double),
+        ("lambda_over_mu", ctypes.c_double),
+        ("entropy_fix", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("ref_state", ctypes.c_int),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("ke", ctypes.c_double), ("enstrophy", ctypes.c_double), ("mass", ctypes.c_double),
+                ("mom", ctypes.c_double * 3), ("energy", ctypes.c_double), ("umax", ctypes.c_double),
+                ("nonfinite", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load ``libsd.so`` and declare its C signatures; raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.sd_params_default.argtypes = [ctypes.POINTER(Params)]
+    L.sd_init.argtypes = [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), vp,
+                          ctypes.POINTER(vp)]
+    L.sd_free.argtypes = [vp]
+    L.sd_set_stream.argtypes = [vp, vp]
+    L.sd_state_size.argtypes = [vp]
+    L.sd_state_size.restype = ctypes.c_longlong
+    L.sd_rhs.argtypes = [vp, vp, vp]
+    L.sd_rk_step.argtypes = [vp, vp, ctypes.c_double]
+    L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
+    L.sd_last_error.argtypes = []
+    L.sd_last_error.restype = ctypes.c_char_p
+    for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
+              "sd_diagnostics"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != SD_OK:
+        raise SDError(rc, load_library().sd_last_error().decode())
+
+
+class SD:
+    """One SD discretisation on a periodic Cartesian box.
+
+    ``nelem``: elements per direction (length 1 or 3); ``p``: degree;
+    ``scheme``: "compact" or "br1"; ``physics``: "diffusion", "pme" or "ns";
+    ``precision``: "fp64", "fp32" or "bf16x3".  Extra keyword arguments set
+    the fields of ``sd_params`` (nu, pme_m, gamma, Re, Ma, Pr, ...).
+    """
+
+    def __init__(self, nelem, p, scheme="compact", physics="ns", precision="fp64", lo=None, hi=None,
+                 **params):
+        import torch
+        L = load_library()
+        nelem = list(nelem)
+        dim = len(nelem)
+        if dim not in (1, 3):
+            raise ValueError("nelem must have 1 or 3 entries")
+        lo = list(lo) if lo is not None else [0.0] * dim
+        hi = list(hi) if hi is not None else [1.0] * dim
+        m = Mesh(dim, (ctypes.c_int * 3)(*(nelem + [1] * (3 - dim))),
+                 (ctypes.c_double * 3)(*(lo + [0.0] * (3 - dim))),
+                 (ctypes.c_double * 3)(*(hi + [1.0] * (3 - dim))))
+        prm = Params()
+        _check(L.sd_params_default(ctypes.byref(prm)))
+        prm.physics = PHYSICS[physics]
+        prm.precision = PRECISIONS[precision]
+        for k, v in params.items():
+            if not hasattr(prm, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(prm, k, v)
+        self.dim, self.p, self.n = dim, p, p + 1
+        self.nelem = nelem
+        self.nv = 5 if physics == "ns" else 1
+        self.ne = 1
+        for v in nelem:
+            self.ne *= v
+        self.shape = (self.ne, self.nv) + (self.n,) * dim
+        self.params = prm
+        self._ctx = ctypes.c_void_p()
+        stream = torch.cuda.current_stream().cuda_stream
+        _check(L.sd_init(ctypes.byref(m), p, SCHEMES[scheme], ctypes.byref(prm), ctypes.c_void_p(stream),
+                         ctypes.byref(self._ctx)))
+        self.size = L.sd_state_size(self._ctx)
+
+    def _stream(self):
+        import torch
+        _check(load_library().sd_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def _check_state(self, u):
+        import torch
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+            raise TypeError("state must be a contiguous float64 CUDA tensor")
+        if u.numel() != self.size:
+            raise ValueError(f"state has {u.numel()} values, expected {self.size}")
+
+    def rhs(self, u, out=None):
+        import torch
+        self._check_state(u)
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_state(out)
+        self._stream()
+        _check(load_library().sd_rhs(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def rk_step(self, u, dt):
+        self._check_state(u)
+        self._stream()
+        _check(load_library().sd_rk_step(self._ctx, ctypes.c_void_p(u.data_ptr()), float(dt)))
+        return u
+
+    def diagnostics(self, u, raise_nonfinite=False):
+        self._check_state(u)
+        self._stream()
+        d = Diag()
+        rc = load_library().sd_diagnostics(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.byref(d))
+        if rc != SD_OK and not (rc == SD_ENONFINITE and not raise_nonfinite):
+            _check(rc)
+        return {"ke": d.ke, "enstrophy": d.enstrophy, "mass": d.mass, "mom": list(d.mom),
+                "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite)}
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            load_library().sd_free(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

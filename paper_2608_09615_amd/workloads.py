@@ -110,38 +110,68 @@ def tgv_domain(L=1.0):
     return (0.0, 0.0, 0.0), (2 * math.pi * L,) * 3
 
 
+def _global_axis(nel_d, lo_d, hi_d, p):
+    xs, _ = gl_nodes(p + 1)
+    h = (hi_d - lo_d) / nel_d
+    return (lo_d + h * np.arange(nel_d)[:, None] + 0.5 * h * (xs[None, :] + 1.0)).ravel()
+
+
+def _to_elements(field, nel, p):
+    """[gz, gy, gx] point field on the global tensor grid -> [ne, n, n, n]."""
+    n = p + 1
+    f = field.reshape(nel[2], n, nel[1], n, nel[0], n).transpose(0, 2, 4, 1, 3, 5)
+    return np.ascontiguousarray(f.reshape(nel[0] * nel[1] * nel[2], n, n, n))
+
+
+def solenoidal_perturbation(nel, p, rng, kmax=4, lo=(0.0, 0.0, 0.0), hi=None):
+    """Random-phase divergence-free velocity field sum_k a_k cos(k.x + phi_k)/|k|^2
+    over integer wavevectors with |k|_inf <= kmax (a_k . k = 0), normalised to
+    unit maximum; returns three [ne, n, n, n] arrays."""
+    if hi is None:
+        hi = (2 * math.pi,) * 3
+    ks = np.arange(-kmax, kmax + 1)
+    KX, KY, KZ = np.meshgrid(ks, ks, ks, indexing="ij")
+    K = np.stack([KX.ravel(), KY.ravel(), KZ.ravel()], axis=1).astype(float)
+    K = K[np.any(K != 0, axis=1)]
+    a = rng.normal(size=(len(K), 3))
+    k2 = np.sum(K * K, axis=1)
+    a -= K * (np.sum(a * K, axis=1) / k2)[:, None]
+    ph = rng.uniform(0.0, 2 * math.pi, len(K))
+    nk = len(ks)
+    coef = np.zeros((3, nk, nk, nk), dtype=complex)
+    idx = (K + kmax).astype(int)
+    for c in range(3):
+        coef[c, idx[:, 0], idx[:, 1], idx[:, 2]] = a[:, c] * np.exp(1j * ph) / k2
+    gx, gy, gz = (_global_axis(nel[d], lo[d], hi[d], p) for d in range(3))
+    ex = np.exp(1j * np.outer(ks, gx))
+    ey = np.exp(1j * np.outer(ks, gy))
+    ez = np.exp(1j * np.outer(ks, gz))
+    out = []
+    for c in range(3):
+        A = np.einsum("abc,cz->abz", coef[c], ez)
+        B = np.einsum("abz,by->azy", A, ey)
+        F = np.einsum("azy,ax->zyx", B, ex).real
+        out.append(F)
+    m = max(np.abs(F).max() for F in out)
+    return [_to_elements(F / m, nel, p) for F in out]
+
+
 def perturbed_tgv_state(nel, p, seed, amp=1e-2, Ma=0.1, gamma=1.4, noise=0.0, kmax=4):
     """TGV with a seeded random phase shift and a random-phase solenoidal
-    velocity perturbation of wavenumbers |k|_inf <= kmax; ``noise`` adds
-    pointwise seeded noise (relative to each variable's scale) that breaks
-    every symmetry of the flow."""
+    velocity perturbation of wavenumbers |k|_inf <= kmax and amplitude amp;
+    ``noise`` adds pointwise seeded noise (uniform in [-noise, noise] on every
+    conservative variable) that breaks every symmetry of the flow."""
     rng = np.random.Generator(np.random.PCG64(seed))
     phase = tuple(rng.uniform(0.0, 2 * math.pi, 3))
     lo, hi = tgv_domain()
     X, Y, Z = points_3d(nel, lo, hi, p)
     rho, u, v, w, pr = tgv_primitive(X, Y, Z, Ma, gamma, phase=phase)
-    du = np.zeros((3,) + X.shape)
     if amp > 0:
-        modes = []
-        for kx in range(-kmax, kmax + 1):
-            for ky in range(-kmax, kmax + 1):
-                for kz in range(-kmax, kmax + 1):
-                    if (kx, ky, kz) != (0, 0, 0):
-                        modes.append((kx, ky, kz))
-        for k in modes:
-            kv = np.array(k, dtype=float)
-            a = rng.normal(size=3)
-            a -= kv * (a @ kv) / (kv @ kv)          # solenoidal: a . k = 0
-            ph = rng.uniform(0, 2 * math.pi)
-            arg = kv[0] * X + kv[1] * Y + kv[2] * Z + ph
-            s = np.cos(arg) / (kv @ kv)
-            for c in range(3):
-                du[c] += a[c] * s
-        du *= amp / max(np.abs(du).max(), 1e-300)
-    U = conservative(rho, u + du[0], v + du[1], w + du[2], pr, gamma)
+        du = solenoidal_perturbation(nel, p, rng, kmax, lo, hi)
+        u, v, w = u + amp * du[0], v + amp * du[1], w + amp * du[2]
+    U = conservative(rho, u, v, w, pr, gamma)
     if noise > 0:
-        scale = np.array([1.0, 1.0, 1.0, 1.0, 1.0])
-        U = U + noise * scale[None, :, None, None, None] * rng.uniform(-1, 1, U.shape)
+        U = U + noise * rng.uniform(-1, 1, U.shape)
     return U
 
 

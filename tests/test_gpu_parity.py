@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: per variable, max |R_gpu - R_oracle| / max |R_oracle| <= 1e-12 in FP64;
+FP32 within the tolerances stated below (normwise, per variable).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2608_09615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32 (reference state removed for Navier-Stokes): contractions in single
+# precision over n <= 7 terms on O(1) data, fluxes in single precision; the
+# bound is a few hundred FP32 ulps of the largest term, normwise.
+FP32_TOL_SCALAR = 2e-5
+FP32_TOL_NS = 2e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def relerr(R, Ro, floor=0.0):
+    """max over variables of max|R - Ro| / max(max|Ro|, floor); the floor is
+    the operator's natural scale where the exact result may vanish."""
+    R = np.asarray(R).reshape(Ro.shape[0], Ro.shape[1], -1)
+    Ro = Ro.reshape(Ro.shape[0], Ro.shape[1], -1)
+    out = []
+    for v in range(Ro.shape[1]):
+        den = max(np.abs(Ro[:, v]).max(), floor)
+        out.append(np.abs(R[:, v] - Ro[:, v]).max() / (den if den > 0 else 1.0))
+    return max(out)
+
+
+def gpu_rhs(torch, U, nel, p, scheme, physics, precision="fp64", lo=None, hi=None, **kw):
+    from paper_2608_09615_amd import SD
+    print(f"[gpu rhs] {physics} {scheme} {precision} p={p} nel={nel}", flush=True)
+    sd = SD(nel, p, scheme=scheme, physics=physics, precision=precision, lo=lo, hi=hi, **kw)
+    u = torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+    R = sd.rhs(u)
+    torch.cuda.synchronize()
+    return R.cpu().numpy().reshape(U.shape), sd
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("physics", ["diffusion", "pme"])
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_1d_parity(torch_cuda, oracle_lib, scheme, physics, precision):
+    for p in range(1, 9):
+        for N in (1, 2, 11):
+            rng = np.random.Generator(np.random.PCG64(100 * p + N))
+            u = rng.uniform(0.2, 1.0, (N, p + 1))
+            coef = 0.7 if physics == "diffusion" else 3.0
+            kw = dict(nu=coef) if physics == "diffusion" else dict(pme_m=coef)
+            R, _ = gpu_rhs(torch_cuda, u[:, None, :], [N], p, scheme, physics, precision, [-1.0], [2.0], **kw)
+            Ro = oracle_lib.rhs_1d(u, p, -1.0, 2.0, scheme=scheme, physics=physics, coef=coef)
+            tol = FP64_TOL if precision == "fp64" else FP32_TOL_SCALAR
+            scale = coef * np.abs(u).max() * (N / 3.0) ** 2 * (p + 1) ** 2
+            assert relerr(R, Ro[:, None, :], scale) < tol, (p, N, relerr(R, Ro[:, None, :], scale))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_3d_scalar_diffusion_parity(torch_cuda, oracle_lib, scheme, precision):
+    prm = oracle_lib.make_params("diffusion", nu=0.9)
+    for p in range(1, 7):
+        for nel in ((3, 4, 5), (1, 2, 3)):
+            U = W.random_scalar_3d(nel, p, seed=p)
+            lo, hi = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+            R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "diffusion", precision, lo, hi, nu=0.9)
+            Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+            tol = FP64_TOL if precision == "fp64" else FP32_TOL_SCALAR
+            scale = 0.9 * np.abs(U).max() * (p + 1) ** 2 / 0.5 ** 2
+            assert relerr(R, Ro, scale) < tol, (p, nel, relerr(R, Ro, scale))
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_3d_ns_parity_fp64(torch_cuda, oracle_lib, scheme, p):
+    prm = oracle_lib.make_params("ns", Re=400.0)
+    lo, hi = W.tgv_domain()
+    for nel in ((3, 4, 5), (2, 1, 3)):
+        U = W.perturbed_tgv_state(nel, p, seed=p, noise=1e-2)
+        R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp64", lo, hi, Re=400.0)
+        Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+        assert relerr(R, Ro) < FP64_TOL, (nel, relerr(R, Ro))
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_3d_ns_parity_fp32(torch_cuda, oracle_lib, scheme, p):
+    prm = oracle_lib.make_params("ns", Re=1600.0)
+    lo, hi = W.tgv_domain()
+    nel = (4, 3, 5)
+    U = W.perturbed_tgv_state(nel, p, seed=10 + p, noise=1e-3)
+    R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp32", lo, hi)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+    err = relerr(R, Ro)
+    print(f"fp32 NS p={p} {scheme}: normwise relative error {err:.3e}")
+    assert err < FP32_TOL_NS
+
+
+@pytest.mark.parametrize("scheme,width", [("compact", 19), ("br1", 25)])
+def test_gpu_stencil_width(torch_cuda, oracle_lib, scheme, width):
+    nel, p = (7, 7, 7), 2
+    lo, hi = W.tgv_domain()
+    U0 = W.perturbed_tgv_state(nel, p, seed=4, noise=1e-3)
+    U1 = U0.copy()
+    U1[3 + 7 * (3 + 7 * 3)] *= 1.001
+    R0, _ = gpu_rhs(torch_cuda, U0, nel, p, scheme, "ns", "fp64", lo, hi)
+    R1, _ = gpu_rhs(torch_cuda, U1, nel, p, scheme, "ns", "fp64", lo, hi)
+    ch = np.abs(R1 - R0).reshape(len(U0), -1).max(1)
+    assert (ch > 1e-13 * np.abs(R0).max()).sum() == width
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_rk4_step_parity(torch_cuda, oracle_lib, scheme):
+    nel, p = (3, 3, 4), 3
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns")
+    U = W.perturbed_tgv_state(nel, p, seed=8, noise=1e-3)
+    from paper_2608_09615_amd import SD
+    sd = SD(nel, p, scheme=scheme, physics="ns", lo=lo, hi=hi)
+    u = torch_cuda.from_numpy(U).to("cuda")
+    dt = 2e-3
+    for _ in range(3):
+        sd.rk_step(u, dt)
+    torch_cuda.cuda.synchronize()
+    Uo = oracle_lib.rk4_3d(U, nel, lo, hi, p, scheme, prm, dt, 3)
+    dU = u.cpu().numpy() - Uo
+    assert np.abs(dU).max() < 1e-12 * np.abs(Uo - U).max() + 1e-13
+
+
+def test_diagnostics_parity(torch_cuda, oracle_lib):
+    nel, p = (4, 3, 5), 3
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns")
+    U = W.perturbed_tgv_state(nel, p, seed=9, noise=1e-3)
+    from paper_2608_09615_amd import SD
+    sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+    d = sd.diagnostics(torch_cuda.from_numpy(U).to("cuda"))
+    do = oracle_lib.diag_3d(U, nel, lo, hi, p, prm)
+    for k in ("ke", "enstrophy", "mass", "energy", "umax"):
+        assert abs(d[k] - do[k]) <= 1e-12 * abs(do[k]), k
+    for i in range(3):
+        assert abs(d["mom"][i] - do[f"mom{i}"]) <= 1e-12 * do["mass"]
+    assert d["nonfinite"] is False
+    U[5, 2, 1, 1, 1] = np.nan
+    d = sd.diagnostics(torch_cuda.from_numpy(U).to("cuda"))
+    assert d["nonfinite"] is True
+
+
+def ulp_sensitivity(oracle_lib, U, nel, lo, hi, p, scheme, prm, sel):
+    """Relative change of the oracle's RHS when every input value moves by
+    about one FP64 ulp: the rounding floor any FP64 evaluation shares."""
+    R = oracle_lib.rhs_3d_elems(U, nel, lo, hi, p, scheme, prm, sel)
+    U2 = U * (1.0 + 2.2e-16 * np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, U.shape))
+    R2 = oracle_lib.rhs_3d_elems(U2, nel, lo, hi, p, scheme, prm, sel)
+    return R, relerr(R2, R)
+
+
+def test_tgv_32cubed_sampled_parity(torch_cuda, oracle_lib):
+    """Full size of the Re = 1600 TGV workload (32^3 elements, p = 3), both
+    schemes and both precisions: sampled elements against the oracle's
+    element-wise RHS.  At this size the RHS moves by ~3e-12 (relative) when
+    the input moves by one ulp (rho E ~ 180 at Ma = 0.1, second derivatives
+    on h = 2 pi/32), so the FP64 bar is max(1e-12, 4 x that sensitivity)."""
+    nel, p = (32, 32, 32), 3
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns", Re=1600.0)
+    U = W.perturbed_tgv_state(nel, p, seed=21, noise=1e-3, amp=1e-2)
+    rng = np.random.Generator(np.random.PCG64(5))
+    sel = np.unique(np.concatenate([rng.integers(0, 32 ** 3, 48), [0, 31, 32 ** 2 - 1, 32 ** 3 - 1]]))
+    for scheme in ("compact", "br1"):
+        Ro, sens = ulp_sensitivity(oracle_lib, U, nel, lo, hi, p, scheme, prm, sel)
+        assert sens < 1e-11
+        for precision, tol in (("fp64", max(FP64_TOL, 4 * sens)), ("fp32", FP32_TOL_NS)):
+            R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", precision, lo, hi)
+            err = relerr(R[sel], Ro)
+            print(f"32^3 {scheme} {precision}: error {err:.3e} (ulp sensitivity {sens:.3e})")
+            assert err < tol, (scheme, precision, err, sens)

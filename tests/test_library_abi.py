@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every symbol of include/sd.h, and rejects
+invalid arguments before touching the device (CPU-only checks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sd_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2608_09615_amd import sd
+    if not os.path.exists(sd.LIB_PATH):
+        pytest.fail("libsd.so is not built (run __graft_entry__.build())")
+    return sd.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "sd_rhs" in names and "sd_init" in names and "sd_rk_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2608_09615_amd import sd
+    assert sorted(sd.EXPORTS) == sorted(n for n in declared_functions() if n in sd.EXPORTS)
+    assert set(sd.EXPORTS) <= set(declared_functions())
+
+
+def _init(lib, dim=3, nel=(4, 4, 4), p=3, scheme=1, **kw):
+    from paper_2608_09615_amd import sd
+    m = sd.Mesh(dim, (ctypes.c_int * 3)(*nel), (ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(1, 1, 1))
+    prm = sd.Params()
+    assert lib.sd_params_default(ctypes.byref(prm)) == 0
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    ctx = ctypes.c_void_p()
+    rc = lib.sd_init(ctypes.byref(m), p, scheme, ctypes.byref(prm), None, ctypes.byref(ctx))
+    return rc, lib.sd_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=2), -1),
+    (dict(nel=(0, 4, 4)), -1),
+    (dict(p=0), -1),
+    (dict(p=9), -1),
+    (dict(scheme=7), -1),
+    (dict(physics=9), -1),
+    (dict(physics=1, pme_m=2.5), -1),
+    (dict(precision=5), -1),
+    (dict(Re=-1.0), -1),
+])
+def test_invalid_arguments_are_rejected(lib, kw, code):
+    rc, msg = _init(lib, **kw)
+    assert rc == code and msg
+
+
+def test_params_default_values(lib):
+    from paper_2608_09615_amd import sd
+    prm = sd.Params()
+    assert lib.sd_params_default(ctypes.byref(prm)) == 0
+    assert prm.physics == 2 and prm.gamma == 1.4 and prm.Re == 1600.0 and prm.Ma == 0.1
+    assert prm.Pr == 0.71 and prm.lambda_over_mu == 0.0 and prm.ref_state == -1
+    assert lib.sd_params_default(None) == -1
+
+
+def test_null_pointers(lib):
+    assert lib.sd_rhs(None, None, None) == -1
+    assert lib.sd_rk_step(None, None, 0.1) == -1
+    assert lib.sd_free(None) == 0
+    assert lib.sd_state_size(None) == -1
