@@ -1,0 +1,196 @@
+"""Throughput of the SD right-hand side on one MI355X.
+
+Workload: compressible Navier-Stokes Taylor-Green vortex, Re = 1600, Ma = 0.1,
+Pr = 0.71, gamma = 1.4 on the periodic box [0, 2 pi]^3 with 32^3 hexahedra
+at p = 3 (2 097 152 solution points, 5 conserved variables), compact scheme.
+One bench step is one classical RK4 step: four right-hand sides and four FP64
+stage updates on the device-resident state.  The metric counts solution
+points (DOF) per RK stage: GDOF/s = n_el (p+1)^3 * 4 * steps / time.
+
+Prints one JSON line.  ``value`` is the FP32 path (contractions and fluxes in
+FP32, reference state removed, FP64 RK accumulation); the FP64 path is timed
+beside it under ``fp64``.  The roofline of the right-hand-side kernels uses
+HIP events recorded by the library around every RHS inside the timed region
+(sd_timing) on the stream the kernels run on.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic work per solution point and RHS at p = 3, Navier-Stokes:
+# contractions 18 nv (n+1) MAC = 450 MAC = 900 flop (interpolation to the three
+# flux-point families, gradient, gradient to flux points, divergence) plus the
+# pointwise fluxes, ~525 flop-equivalents (sqrt, division counted as one).
+FLOP_PER_DOF = {3: 900.0 + 525.0, 5: 1260.0 + 480.0}
+# Algorithmic bytes per solution point and RHS: read u, write du/dt, FP64.
+BYTES_PER_DOF = 80.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30, help="timed RK4 steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nel", type=int, default=32)
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--scheme", default="compact")
+    ap.add_argument("--ke-steps", type=int, default=150, help="RK4 steps of the FP32-vs-FP64 KE check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=6144, help="elements in the oracle sample")
+    return ap.parse_args()
+
+
+def run_path(torch, W, args, precision, U0, dt):
+    from paper_2608_09615_amd import SD
+    lo, hi = W.tgv_domain()
+    nel = (args.nel,) * 3
+    sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi,
+            Re=1600.0, Ma=0.1, Pr=0.71, gamma=1.4)
+    u = torch.from_numpy(U0).to("cuda")
+    for _ in range(args.warmup):
+        sd.rk_step(u, dt)
+    torch.cuda.synchronize()
+    sd.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sd.rk_step(u, dt)
+    diag = sd.diagnostics(u)                  # synchronises the stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rhs_ms, rhs_count = sd.timing_read()
+    sd.timing(False)
+    ne = args.nel ** 3
+    dof = ne * (args.p + 1) ** 3
+    sec = t1 - t0
+    stages = 4 * args.steps
+    out = {
+        "gdofs": dof * stages / sec / 1e9,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "rhs_ms_avg": rhs_ms / max(rhs_count, 1),
+        "rhs_count": rhs_count,
+        "ke_end": diag["ke"],
+        "nonfinite": diag["nonfinite"],
+    }
+    sd.close()
+    return out
+
+
+def ke_error(torch, W, args, U0, dt, nsteps):
+    """max_t |KE_fp32 - KE_fp64| / KE_fp64(0) over nsteps RK4 steps."""
+    from paper_2608_09615_amd import SD
+    lo, hi = W.tgv_domain()
+    nel = (args.nel,) * 3
+    hist = {}
+    for precision in ("fp64", "fp32"):
+        sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi)
+        u = torch.from_numpy(U0).to("cuda")
+        h = [sd.diagnostics(u)["ke"]]
+        for s in range(nsteps):
+            sd.rk_step(u, dt)
+            if (s + 1) % 10 == 0:
+                h.append(sd.diagnostics(u)["ke"])
+        hist[precision] = h
+        sd.close()
+    k64, k32 = hist["fp64"], hist["fp32"]
+    return max(abs(a - b) for a, b in zip(k32, k64)) / k64[0], nsteps * dt
+
+
+def cpu_baseline(W, args, U0):
+    import numpy as np
+    from oracle import oracle as O
+    lo, hi = W.tgv_domain()
+    nel = (args.nel,) * 3
+    ne = args.nel ** 3
+    threads = min(os.cpu_count() or 1, 16)
+    n = min(args.cpu_sample, ne)
+    sel = np.arange(n, dtype=np.int64)
+    prm = O.make_params("ns", Re=1600.0, Ma=0.1, Pr=0.71)
+    t0 = time.perf_counter()
+    O.rhs_3d_elems(U0, nel, lo, hi, args.p, args.scheme, prm, sel, nthreads=threads)
+    sec = time.perf_counter() - t0
+    return {"value": n * (args.p + 1) ** 3 / sec / 1e9, "unit": "GDOF/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one RHS on the first {n} of {ne} elements of the same TGV state "
+                      f"({sec:.1f} s wall, OpenMP over elements)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the right-hand side is "
+              "not sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2608_09615_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    nel = (args.nel,) * 3
+    U0 = W.tgv_state(nel, args.p)
+    h = 2 * math.pi / args.nel
+    c0 = math.sqrt(1.4 * (1.0 / 1.4 / 0.01) / 1.0)
+    dt = 0.3 * h / ((args.p + 1) * (1.0 + c0))
+    print(f"bench: TGV {nel} p={args.p} {args.scheme} dt={dt:.3e}", file=sys.stderr, flush=True)
+    r32 = run_path(torch, W, args, "fp32", U0, dt)
+    print(f"bench: fp32 {r32['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    r64 = run_path(torch, W, args, "fp64", U0, dt)
+    print(f"bench: fp64 {r64['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    kerr, tke = ke_error(torch, W, args, U0, dt, args.ke_steps) if args.ke_steps > 0 else (None, 0.0)
+    dof = args.nel ** 3 * (args.p + 1) ** 3
+    flop = FLOP_PER_DOF.get(args.p, 1430.0) * dof
+
+    def roof(r, peak_flops, name):
+        t = r["rhs_ms_avg"] * 1e-3
+        alu = flop / t / 1e12
+        hbm = BYTES_PER_DOF * dof / t / 1e9
+        # binding ceiling: the lower of the ALU and HBM rooflines for this path
+        ceil_alu = peak_flops * 1e12 / FLOP_PER_DOF.get(args.p, 1430.0)
+        ceil_hbm = PEAK_HBM_GBS * 1e9 / BYTES_PER_DOF
+        if ceil_alu <= ceil_hbm:
+            return {"bound": "alu", "achieved": alu, "peak": peak_flops, "unit": "TFLOP/s",
+                    "frac": alu / peak_flops, "traffic": None, "kernels": name,
+                    "rhs_ms": r["rhs_ms_avg"], "hbm_gbs_algorithmic": hbm}
+        return {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": hbm / PEAK_HBM_GBS, "traffic": None, "kernels": name,
+                "rhs_ms": r["rhs_ms_avg"], "tflops_algorithmic": alu}
+
+    rec = {
+        "metric": "SD RHS GDOF/s per RK stage",
+        "value": r32["gdofs"],
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"TGV Re=1600 Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}",
+                   "dof": dof, "step": "one RK4 step = 4 RHS + 4 FP64 stage updates",
+                   "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
+        "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs"),
+        "fp64": {"value": r64["gdofs"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                 "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_traces+k_rhs")},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(W, args, U0)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

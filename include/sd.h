@@ -134,6 +134,15 @@ int sd_rk_step(sd_ctx *ctx, double *u, double dt);
  * SD_ENONFINITE (with *out filled) when the state holds NaN or Inf. */
 int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
 
+/* Timing of the right-hand side kernels: with enable = 1 every later RHS
+ * evaluation of the context (sd_rhs and the four inside sd_rk_step) is
+ * bracketed by a pair of HIP events on the context's stream (up to 4096
+ * evaluations; later ones go untimed); enable = 0 stops recording.
+ * sd_timing_read waits for the stream and returns the summed elapsed time
+ * (ms) and the number of timed evaluations since the last enable. */
+int sd_timing(sd_ctx *ctx, int enable);
+int sd_timing_read(sd_ctx *ctx, double *total_ms, long long *count);
+
 /* Message of the last error on this thread ("" if none). */
 const char *sd_last_error(void);
 

@@ -467,4 +467,5 @@ __global__ void k_diag_final(const double *__restrict__ part, int nparts, double
 
 }  // namespace sd
 
+#include "sd_ns_kernel.h"
 #include "sd_dispatch.inc"

@@ -21,6 +21,13 @@ struct NsConst {
         lam_over_mu((R)a.lam_over_mu), cp_over_pr((R)a.cp_over_pr), efix((R)a.efix), suth(a.suth) {}
 };
 
+// Component d of a 3-vector without runtime indexing of a private array
+// (which would put the array in scratch memory).
+template <typename R>
+__device__ __forceinline__ R pick(int d, R a0, R a1, R a2) {
+  return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
 // Primitive quantities of a (reference-shifted) conservative state.
 template <typename R>
 struct Prim {
@@ -45,12 +52,10 @@ __device__ __forceinline__ Prim<R> ns_prim(const NsConst<R> &c, const R *U) {
 // F_c e_d - F_c(U0) e_d
 template <typename R>
 __device__ __forceinline__ void ns_conv(const NsConst<R> &c, const R *U, const Prim<R> &s, int d, R *F) {
-  R ud = s.u[d];
-  F[0] = U[1 + d];
-  F[1] = U[1] * ud;
-  F[2] = U[2] * ud;
-  F[3] = U[3] * ud;
-  F[1 + d] += s.dp;
+  R ud = pick(d, s.u[0], s.u[1], s.u[2]);
+  F[0] = pick(d, U[1], U[2], U[3]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[1 + i] = U[1 + i] * ud + (i == d ? s.dp : R(0));
   F[4] = (s.rhoE + s.p) * ud;
 }
 
@@ -78,13 +83,16 @@ __device__ __forceinline__ void ns_visc(const NsConst<R> &c, const Prim<R> &s, c
   R div = du[0][0] + du[1][1] + du[2][2];
   R tau[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) tau[i] = mu * (du[i][d] + du[d][i]);
-  tau[d] += lam * div;
+  for (int i = 0; i < 3; ++i) {
+    R dud = pick(d, du[i][0], du[i][1], du[i][2]);   // d u_i / d x_d
+    R ddu = pick(d, du[0][i], du[1][i], du[2][i]);   // d u_d / d x_i
+    tau[i] = mu * (dud + ddu) + (i == d ? lam * div : R(0));
+  }
   F[0] = R(0);
   F[1] = tau[0];
   F[2] = tau[1];
   F[3] = tau[2];
-  F[4] = s.u[0] * tau[0] + s.u[1] * tau[1] + s.u[2] * tau[2] + kappa * dT[d];
+  F[4] = s.u[0] * tau[0] + s.u[1] * tau[1] + s.u[2] * tau[2] + kappa * pick(d, dT[0], dT[1], dT[2]);
 }
 
 // Roe flux along e_d with Harten's fix on the acoustic waves, minus F_c(U0).
@@ -105,11 +113,11 @@ __device__ __forceinline__ void ns_roe(const NsConst<R> &c, const R *UL, const R
   R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
   R c2 = c.gm1 * (Ht - R(0.5) * q2);
   R cs = sqrt(c2);
-  R un = ut[d];
+  R un = pick(d, ut[0], ut[1], ut[2]);
   R du[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) du[i] = Rr.u[i] - L.u[i];
-  R drho = Rr.rho - L.rho, dpj = Rr.dp - L.dp, dun = du[d];
+  R drho = Rr.rho - L.rho, dpj = Rr.dp - L.dp, dun = pick(d, du[0], du[1], du[2]);
   R inv2c2 = R(0.5) / c2;
   R a1 = (dpj - rt * cs * dun) * inv2c2;
   R a5 = (dpj + rt * cs * dun) * inv2c2;
@@ -122,14 +130,12 @@ __device__ __forceinline__ void ns_roe(const NsConst<R> &c, const R *UL, const R
   }
   R dut[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) dut[i] = du[i];
-  dut[d] = R(0);
+  for (int i = 0; i < 3; ++i) dut[i] = i == d ? R(0) : du[i];
   R w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2, ws = l2 * rt;
   R D[5];
   D[0] = w1 + w2 + w5;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) D[1 + i] = (w1 + w5 + w2) * ut[i] + ws * dut[i];
-  D[1 + d] += (w5 - w1) * cs;
+  for (int i = 0; i < 3; ++i) D[1 + i] = (w1 + w5 + w2) * ut[i] + ws * dut[i] + (i == d ? (w5 - w1) * cs : R(0));
   D[4] = w1 * (Ht - cs * un) + w5 * (Ht + cs * un) + w2 * R(0.5) * q2 +
          ws * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]);
 #pragma unroll
@@ -160,6 +166,7 @@ __device__ __forceinline__ void interior_flux(const KArgs &a, int d, const R *U,
   } else {
     F[0] = -(R)a.nu * G[d];
   }
+  (void)NV;
 }
 
 // Interface flux along d: Roe on the two traces minus the viscous flux of

@@ -16,7 +16,7 @@ PHYSICS = {"diffusion": 0, "pme": 1, "ns": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
-           "sd_rk_step", "sd_diagnostics", "sd_last_error"]
+           "sd_rk_step", "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_last_error"]
 
 
 class SDError(RuntimeError):
@@ -79,10 +79,12 @@ def load_library(path=LIB_PATH):
     L.sd_rhs.argtypes = [vp, vp, vp]
     L.sd_rk_step.argtypes = [vp, vp, ctypes.c_double]
     L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
+    L.sd_timing.argtypes = [vp, ctypes.c_int]
+    L.sd_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
-              "sd_diagnostics"):
+              "sd_diagnostics", "sd_timing", "sd_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -173,6 +175,17 @@ class SD:
             _check(rc)
         return {"ke": d.ke, "enstrophy": d.enstrophy, "mass": d.mass, "mom": list(d.mom),
                 "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite)}
+
+    def timing(self, enable=True):
+        """Start (or stop) recording HIP events around every RHS evaluation."""
+        _check(load_library().sd_timing(self._ctx, 1 if enable else 0))
+
+    def timing_read(self):
+        """(total ms, number of timed RHS evaluations) since timing() began."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_longlong()
+        _check(load_library().sd_timing_read(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
