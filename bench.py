@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--scheme", default="compact")
     ap.add_argument("--ke-steps", type=int, default=150, help="RK4 steps of the FP32-vs-FP64 KE check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=6144, help="elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device to device (calibrates byte counters)")
+    ap.add_argument("--precisions", default="fp32,fp64")
     return ap.parse_args()
 
 
@@ -144,10 +147,22 @@ def main():
     c0 = math.sqrt(1.4 * (1.0 / 1.4 / 0.01) / 1.0)
     dt = 0.3 * h / ((args.p + 1) * (1.0 + c0))
     print(f"bench: TGV {nel} p={args.p} {args.scheme} dt={dt:.3e}", file=sys.stderr, flush=True)
-    r32 = run_path(torch, W, args, "fp32", U0, dt)
-    print(f"bench: fp32 {r32['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
-    r64 = run_path(torch, W, args, "fp64", U0, dt)
-    print(f"bench: fp64 {r64['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copy probe {args.copy_probe_mib} MiB", file=sys.stderr, flush=True)
+        del src, dst
+    precs = args.precisions.split(",")
+    r32 = run_path(torch, W, args, "fp32", U0, dt) if "fp32" in precs else None
+    if r32:
+        print(f"bench: fp32 {r32['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    r64 = run_path(torch, W, args, "fp64", U0, dt) if "fp64" in precs else None
+    if r64:
+        print(f"bench: fp64 {r64['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    if r32 is None or r64 is None:
+        return
     kerr, tke = ke_error(torch, W, args, U0, dt, args.ke_steps) if args.ke_steps > 0 else (None, 0.0)
     dof = args.nel ** 3 * (args.p + 1) ** 3
     flop = FLOP_PER_DOF.get(args.p, 1430.0) * dof

@@ -3,20 +3,26 @@
 // Same algebra as the generic k_rhs (see sd_kernels.hip), organised for the
 // five-variable system:
 //   P0  per element: neighbour indices once (6 face + 12 edge neighbours,
-//       32-bit arithmetic); the state (reference removed) and the
-//       neighbours' face traces T, normal-gradient traces NN and edge traces
-//       staged in LDS with coalesced loads;
-//   P1  own face traces (and, compact, own normal-gradient traces) from the
-//       LDS state: no re-read of the trace buffer;
-//   P2  auxiliary gradient at the solution points (15 components);
-//   P3  one work item per face point: the common gradient (own side from the
+//       32-bit arithmetic); the state (reference removed), the neighbours'
+//       face traces T and normal-gradient traces NN, and the edge traces
+//       staged in LDS with vector loads;
+//   P2  auxiliary gradient at the solution points (15 components); the own
+//       face traces it needs come from the same state values;
+//   P3  one work item per face point: own trace (and, compact, normal-gradient
+//       trace) from the state, the common gradient (own side from the
 //       gradient, neighbour side rebuilt from its traces and the edge traces)
 //       and the interface flux (Roe minus viscous), kept in LDS;
 //   P4  one work item per line of a flux-point family: the line's state and
 //       gradient in registers, the n-1 interior fluxes, the two interface
 //       fluxes, and the divergence along the line (-2/h_d M F);
 //   P5  the three directional contributions summed and stored in FP64.
+// Work items of P3 and P4 are ordered face-major (direction-major for
+// P4) so that, with epb * n^2 = 64 (p = 3, four elements per block), every
+// wavefront works on a single face direction: the bodies are compiled per
+// direction and the direction branches are uniform.
 #pragma once
+
+#include <type_traits>
 
 #include "sd_internal.h"
 #include "sd_physics.h"
@@ -36,37 +42,292 @@ struct NsOps {
   R kap[2];
 };
 
+__host__ __device__ constexpr int pad4(int x) { return (x + 3) / 4 * 4; }
+
 template <int N>
 struct NsSmem {
   static constexpr int NP = N * N * N, NF = N * N;
-  static constexpr int U = 0;                  // [5][NP]
-  static constexpr int G = U + 5 * NP;         // [3][5][NP]
-  static constexpr int TO = G + 15 * NP;       // [6][5][NF] own traces
-  static constexpr int TN = TO + 30 * NF;      // [6][5][NF] neighbour traces
-  static constexpr int NO = TN + 30 * NF;      // [6][5][NF] own normal-gradient traces
-  static constexpr int NN = NO + 30 * NF;      // [6][5][NF] neighbour normal-gradient traces
-  static constexpr int E = NN + 30 * NF;       // [12][5][N] edge-neighbour edge traces
-  static constexpr int FH = E + 60 * N;        // [6][5][NF] interface fluxes
-  static constexpr int RS = TO;                // [3][5][NP] aliases TO..E after P3
-  static constexpr int TOTAL = FH + 30 * NF;
-  static_assert(RS + 15 * NP <= FH, "partial residuals overlap the interface fluxes");
+  static constexpr int U = 0;                        // [5][NP]
+  static constexpr int G = pad4(U + 5 * NP);         // [3][5][NP]
+  static constexpr int TNN = pad4(G + 15 * NP);      // [6][10][NF] neighbour T (v < 5) and NN (v >= 5)
+  static constexpr int E = pad4(TNN + 60 * NF);      // [12][5][N] edge-neighbour edge traces
+  static constexpr int FH = pad4(E + 60 * N);        // [6][5][NF] interface fluxes
+  static constexpr int END = pad4(FH + 30 * NF);
+  // [3][5][NP] partial residuals: alias TNN..E (dead after P3) when they fit
+  static constexpr int RS = (TNN + 15 * NP <= FH) ? TNN : END;
+  static constexpr int TOTAL = (RS == TNN) ? END : pad4(END + 15 * NP);
 };
+
+// number of values moved per vector load for a contiguous run of CNT values
+template <typename R, int CNT>
+__host__ __device__ constexpr int vec_width() {
+  return sizeof(R) == 4 ? (CNT % 4 == 0 ? 4 : (CNT % 2 == 0 ? 2 : 1)) : (CNT % 2 == 0 ? 2 : 1);
+}
+
+template <typename R, int W>
+struct VecT;
+template <> struct VecT<float, 4> { using T = float4; };
+template <> struct VecT<float, 2> { using T = float2; };
+template <> struct VecT<float, 1> { using T = float; };
+template <> struct VecT<double, 2> { using T = double2; };
+template <> struct VecT<double, 1> { using T = double; };
+
+// interface flux at face point q of face (D, S)
+template <int N, typename R, bool COMPACT, int D, int S>
+__device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q) {
+  using SM = NsSmem<N>;
+  constexpr int NP = SM::NP, NF = SM::NF, f = 2 * D + S, SO = 1 - S;
+  R UL[5], UR[5], Uh[5], Vh[15], NNo[5];
+  const R thd = (R)a.two_over_h[D];
+  int base, stride;
+  line_of<3, N>(D, q, base, stride);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    // own face trace (and, compact, own normal-gradient trace) from the state
+    const R *u = E + SM::U + v * NP + base;
+    R own = R(0), nn = R(0);
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      R uv = u[c * stride];
+      own += op.Lend[S][c] * uv;
+      if constexpr (COMPACT) nn += op.rrow[S][c] * uv;
+    }
+    NNo[v] = nn;
+    R oth = E[SM::TNN + (f * 10 + v) * NF + q];
+    UL[v] = S == 0 ? oth : own;
+    UR[v] = S == 0 ? own : oth;
+    Uh[v] = S == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
+  }
+  // normal component: one-sided (compact) or standard (BR1) on each side
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    R vown;
+    if constexpr (COMPACT) {
+      vown = thd * (NNo[v] + op.kap[S] * Uh[v]);
+    } else {
+      const R *g = E + SM::G + (D * 5 + v) * NP + base;
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += op.Lend[S][c] * g[c * stride];
+      vown = acc;
+    }
+    R voth = thd * (E[SM::TNN + (f * 10 + 5 + v) * NF + q] + op.kap[SO] * Uh[v]);
+    Vh[D * 5 + v] = S == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
+  }
+  // transverse components: the standard gradient on both sides
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm) {
+    const int m = (D + 1 + mm) % 3;        // compile-time after unrolling
+    const int t3 = 3 - D - m;
+    const int a_lo = q % N, a_hi = q / N;
+    const int am = (m < t3) ? a_lo : a_hi, at = (m < t3) ? a_hi : a_lo;
+    const int qs = (m < t3) ? at * N : at, qstep = (m < t3) ? 1 : N;
+    const R thm = (R)a.two_over_h[m];
+    const int e0i = edge_id(D, S, m, 0), e1i = edge_id(D, S, m, 1);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const R *g = E + SM::G + (m * 5 + v) * NP + base;
+      R vown = R(0);
+#pragma unroll
+      for (int c = 0; c < N; ++c) vown += op.Lend[S][c] * g[c * stride];
+      const R *tn = E + SM::TNN + (f * 10 + v) * NF + qs;
+      R dT = R(0), eL = R(0), eR = R(0);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        R tv = tn[c * qstep];
+        dT += op.D[am][c] * tv;
+        eL += op.Lend[0][c] * tv;
+        eR += op.Lend[1][c] * tv;
+      }
+      R eLn = E[SM::E + (e0i * 5 + v) * N + at];
+      R eRn = E[SM::E + (e1i * 5 + v) * N + at];
+      R ehL = R(0.5) * (eLn + eL), ehR = R(0.5) * (eR + eRn);
+      R voth = thm * (dT + op.Mc[0][am] * (ehL - eL) + op.Mc[1][am] * (ehR - eR));
+      Vh[m * 5 + v] = S == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
+    }
+  }
+  R F[5];
+  face_flux<PHYS_NS, 5, R>(a, D, UL, UR, Uh, Vh, F);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) E[SM::FH + (f * 5 + v) * NF + q] = F[v];
+}
+
+// interior fluxes and divergence along line q of flux-point family D
+template <int N, typename R, int D>
+__device__ __forceinline__ void ns_line_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q) {
+  using SM = NsSmem<N>;
+  constexpr int NP = SM::NP, NF = SM::NF;
+  int base, stride;
+  line_of<3, N>(D, q, base, stride);
+  R ul[5][N], gl[15][N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ul[v][c] = E[SM::U + v * NP + base + c * stride];
+#pragma unroll
+    for (int w = 0; w < 15; ++w) gl[w][c] = E[SM::G + w * NP + base + c * stride];
+  }
+  R Fl[N + 1][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    Fl[0][v] = E[SM::FH + ((2 * D) * 5 + v) * NF + q];
+    Fl[N][v] = E[SM::FH + ((2 * D + 1) * 5 + v) * NF + q];
+  }
+#pragma unroll
+  for (int rr = 1; rr < N; ++rr) {
+    R Uf[5], Gf[15];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * ul[v][c];
+      Uf[v] = acc;
+    }
+#pragma unroll
+    for (int w = 0; w < 15; ++w) {
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * gl[w][c];
+      Gf[w] = acc;
+    }
+    interior_flux<PHYS_NS, 5, R>(a, D, Uf, Gf, Fl[rr]);
+  }
+  const R thd = (R)a.two_over_h[D];
+#pragma unroll
+  for (int ai = 0; ai < N; ++ai)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c <= N; ++c) acc += op.M[ai][c] * Fl[c][v];
+      E[SM::RS + (D * 5 + v) * NP + base + ai * stride] = -thd * acc;
+    }
+}
+
+// What the right-hand-side kernel does with R at the solution points:
+// mode 0 stores it; mode 1 applies one classical RK4 stage in FP64,
+//   acc <- first ? R : acc + c R,  out <- u0 + a R      (stages 1-3)
+//   out <- u0 + dt6 (acc + R)                          (last stage, out = u0)
+// Every block reads its own elements' state before writing them, and other
+// blocks only read the trace buffer, so out may alias the input state.
+struct RkEpi {
+  int mode, first, last;
+  double a, c, dt6;
+  const double *u0;
+  double *acc;
+  double *out;
+};
+
+// Element-local trace kernel for the Navier-Stokes system: the full trace
+// record of every element (face traces T, normal-gradient traces NN, edge
+// traces) is assembled in LDS and stored with contiguous vector stores.
+template <int N, typename R>
+__global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U, R *__restrict__ X, KArgs a,
+                                                   NsOps<N, R> op) {
+  constexpr int NP = N * N * N, NF = N * N;
+  constexpr int XS = trace_stride(3, N, 5), FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
+  constexpr int PER = pad4(5 * NP) + pad4(XS);
+  extern __shared__ double2 smem_tr[];
+  R *sm = reinterpret_cast<R *>(smem_tr);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int epb = a.epb;
+  const int e0 = blockIdx.x * epb;
+  const int nb = min(epb, (int)(a.ne - e0));
+  {
+    constexpr int W = (NP % 2 == 0) ? 2 : 1;
+    using V = typename VecT<double, W>::T;
+    const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
+    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
+      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
+      double u0 = a.U0[r / NP];
+      R *dst = sm + el * PER + r;
+      if constexpr (W == 2) {
+        V x = src[t];
+        dst[0] = (R)(x.x - u0);
+        dst[1] = (R)(x.y - u0);
+      } else {
+        dst[0] = (R)(src[t] - u0);
+      }
+    }
+  }
+  __syncthreads();
+  // face traces and normal-gradient traces, face-major work items
+  for (int t = tid; t < 6 * epb * NF; t += nth) {
+    int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+    if (el >= nb) continue;
+    const R *u = sm + el * PER;
+    R *x = sm + el * PER + pad4(5 * NP);
+    auto item = [&](auto Dc, auto Sc) {
+      constexpr int D = decltype(Dc)::value, S = decltype(Sc)::value, ff = 2 * D + S;
+      int base, stride;
+      line_of<3, N>(D, q, base, stride);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        R tr = R(0), nn = R(0);
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          R uv = u[v * NP + base + c * stride];
+          tr += op.Lend[S][c] * uv;
+          nn += op.rrow[S][c] * uv;
+        }
+        x[ff * FS + v * NF + q] = tr;
+        x[ff * FS + 5 * NF + v * NF + q] = nn;
+      }
+    };
+    using Z = std::integral_constant<int, 0>;
+    using O = std::integral_constant<int, 1>;
+    using T2 = std::integral_constant<int, 2>;
+    switch (f) {
+      case 0: item(Z{}, Z{}); break;
+      case 1: item(Z{}, O{}); break;
+      case 2: item(O{}, Z{}); break;
+      case 3: item(O{}, O{}); break;
+      case 4: item(T2{}, Z{}); break;
+      default: item(T2{}, O{}); break;
+    }
+  }
+  __syncthreads();
+  // edge traces from the face traces: edge (lo, s_lo; hi, s_hi) is the face
+  // trace of (lo, s_lo) interpolated along hi to side s_hi
+  for (int t = tid; t < nb * 12 * 5 * N; t += nth) {
+    int el = t / (60 * N), r = t % (60 * N);
+    int ed = r / (5 * N), w = r % (5 * N), v = w / N, at = w % N;
+    int P = ed >> 2, slo = (ed >> 1) & 1, shi = ed & 1;
+    int lo = P == 2 ? 1 : 0, hi = P == 0 ? 1 : 2, t3 = 3 - lo - hi;
+    R *x = sm + el * PER + pad4(5 * NP);
+    const R *tf = x + (2 * lo + slo) * FS + v * NF;
+    R acc = R(0);
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc += op.Lend[shi][c] * tf[(hi < t3) ? (at * N + c) : (c * N + at)];
+    x[EO + (ed * 5 + v) * N + at] = acc;
+  }
+  __syncthreads();
+  {
+    constexpr int W = vec_width<R, XS>();
+    using V = typename VecT<R, W>::T;
+    V *dst = reinterpret_cast<V *>(X + (long long)e0 * XS);
+    for (int t = tid; t < nb * XS / W; t += nth) {
+      int el = (t * W) / XS, r = (t * W) % XS;
+      dst[t] = *reinterpret_cast<const V *>(sm + el * PER + pad4(5 * NP) + r);
+    }
+  }
+}
 
 template <int N, typename R, bool COMPACT>
 __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
-                                                double *__restrict__ dudt, KArgs a, NsOps<N, R> op) {
+                                                double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep) {
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   constexpr int XS = trace_stride(3, N, 5), FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
-  extern __shared__ char smem_raw[];
-  R *sm = reinterpret_cast<R *>(smem_raw);
+  extern __shared__ double2 smem_ns[];          // 16-byte aligned dynamic LDS
+  R *sm = reinterpret_cast<R *>(smem_ns);
   __shared__ int snb[kNsMaxEpb][18];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int epb = a.epb;
   const int e0 = blockIdx.x * epb;
   const int nb = min(epb, (int)(a.ne - e0));
 
-  // P0: neighbour table, state, neighbour traces
+  // P0: neighbour table and state
   for (int t = tid; t < nb * 18; t += nth) {
     int el = t / 18, k = t % 18;
     int e = e0 + el;
@@ -84,43 +345,45 @@ __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, co
     }
     snb[el][k] = c[0] + nx * (c[1] + ny * c[2]);
   }
-  for (int t = tid; t < nb * 5 * NP; t += nth) {
-    int el = t / (5 * NP), r = t % (5 * NP);
-    sm[el * SM::TOTAL + SM::U + r] = (R)(U[(long long)e0 * 5 * NP + t] - a.U0[r / NP]);
+  {
+    constexpr int W = (NP % 2 == 0) ? 2 : 1;
+    using V = typename VecT<double, W>::T;
+    const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
+    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
+      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
+      double u0 = a.U0[r / NP];
+      R *dst = sm + el * SM::TOTAL + SM::U + r;
+      if constexpr (W == 2) {
+        V x = src[t];
+        dst[0] = (R)(x.x - u0);
+        dst[1] = (R)(x.y - u0);
+      } else {
+        dst[0] = (R)(src[t] - u0);
+      }
+    }
   }
   __syncthreads();
-  for (int t = tid; t < nb * 60 * NF; t += nth) {
-    int el = t / (60 * NF), r = t % (60 * NF);
-    int f = r / (10 * NF), w = r % (10 * NF);
-    int d = f >> 1, s = f & 1;
-    R val = X[(long long)snb[el][f] * XS + (2 * d + 1 - s) * FS + w];
-    if (w < 5 * NF) sm[el * SM::TOTAL + SM::TN + f * 5 * NF + w] = val;
-    else sm[el * SM::TOTAL + SM::NN + f * 5 * NF + (w - 5 * NF)] = val;
+  // neighbour traces (T and NN of the shared face) and edge traces
+  {
+    constexpr int CNT = 10 * NF, W = vec_width<R, CNT>();
+    using V = typename VecT<R, W>::T;
+    for (int t = tid; t < nb * 6 * CNT / W; t += nth) {
+      int el = t / (6 * CNT / W), r = t % (6 * CNT / W);
+      int f = r / (CNT / W), w = r % (CNT / W);
+      int d = f >> 1, s = f & 1;
+      const V *src = reinterpret_cast<const V *>(X + (long long)snb[el][f] * XS + (2 * d + 1 - s) * FS);
+      reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::TNN + f * CNT)[w] = src[w];
+    }
   }
-  for (int t = tid; t < nb * 60 * N; t += nth) {
-    int el = t / (60 * N), r = t % (60 * N);
-    int ed = r / (5 * N), w = r % (5 * N);
-    int opp = (ed & ~3) + 2 * (1 - ((ed >> 1) & 1)) + (1 - (ed & 1));
-    sm[el * SM::TOTAL + SM::E + ed * 5 * N + w] = X[(long long)snb[el][6 + ed] * XS + EO + opp * 5 * N + w];
-  }
-  // P1: own traces from the staged state
-  for (int t = tid; t < nb * 6 * NF; t += nth) {
-    int el = t / (6 * NF), r = t % (6 * NF);
-    int f = r / NF, q = r % NF, d = f >> 1, s = f & 1, base, stride;
-    line_of<3, N>(d, q, base, stride);
-    R *E = sm + el * SM::TOTAL;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const R *u = E + SM::U + v * NP + base;
-      R tr = R(0), nn = R(0);
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        R uv = u[c * stride];
-        tr += op.Lend[s][c] * uv;
-        if constexpr (COMPACT) nn += op.rrow[s][c] * uv;
-      }
-      E[SM::TO + (f * 5 + v) * NF + q] = tr;
-      if constexpr (COMPACT) E[SM::NO + (f * 5 + v) * NF + q] = nn;
+  {
+    constexpr int CNT = 5 * N, W = vec_width<R, CNT>();
+    using V = typename VecT<R, W>::T;
+    for (int t = tid; t < nb * 12 * CNT / W; t += nth) {
+      int el = t / (12 * CNT / W), r = t % (12 * CNT / W);
+      int ed = r / (CNT / W), w = r % (CNT / W);
+      int opp = (ed & ~3) + 2 * (1 - ((ed >> 1) & 1)) + (1 - (ed & 1));
+      const V *src = reinterpret_cast<const V *>(X + (long long)snb[el][6 + ed] * XS + EO + opp * CNT);
+      reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::E + ed * CNT)[w] = src[w];
     }
   }
   __syncthreads();
@@ -137,11 +400,16 @@ __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, co
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const R *u = E + SM::U + v * NP + base;
-        R acc = R(0);
+        R acc = R(0), to0 = R(0), to1 = R(0);
 #pragma unroll
-        for (int c = 0; c < N; ++c) acc += op.D[am][c] * u[c * stride];
-        int i0 = ((2 * m) * 5 + v) * NF + qm, i1 = ((2 * m + 1) * 5 + v) * NF + qm;
-        R to0 = E[SM::TO + i0], tn0 = E[SM::TN + i0], to1 = E[SM::TO + i1], tn1 = E[SM::TN + i1];
+        for (int c = 0; c < N; ++c) {
+          R uv = u[c * stride];
+          acc += op.D[am][c] * uv;
+          to0 += op.Lend[0][c] * uv;      // own traces at the two m-faces
+          to1 += op.Lend[1][c] * uv;
+        }
+        R tn0 = E[SM::TNN + ((2 * m) * 10 + v) * NF + qm];
+        R tn1 = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + qm];
         R uh0 = R(0.5) * (tn0 + to0), uh1 = R(0.5) * (to1 + tn1);
         acc += op.Mc[0][am] * (uh0 - to0);
         acc += op.Mc[1][am] * (uh1 - to1);
@@ -150,135 +418,50 @@ __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, co
     }
   }
   __syncthreads();
-  // P3: interface fluxes, one work item per face point
-  for (int t = tid; t < nb * 6 * NF; t += nth) {
-    int el = t / (6 * NF), r = t % (6 * NF);
-    int f = r / NF, q = r % NF, d = f >> 1, s = f & 1, so = 1 - s;
-    const R *E = sm + el * SM::TOTAL;
-    R UL[5], UR[5], Uh[5], Vh[15];
-    const R thd = (R)a.two_over_h[d];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      int fv = (f * 5 + v) * NF + q;
-      R own = E[SM::TO + fv], oth = E[SM::TN + fv];
-      UL[v] = s == 0 ? oth : own;
-      UR[v] = s == 0 ? own : oth;
-      Uh[v] = s == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
+  // P3: interface fluxes, face-major work items
+  for (int t = tid; t < 6 * epb * NF; t += nth) {
+    int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+    if (el >= nb) continue;
+    R *E = sm + el * SM::TOTAL;
+    switch (f) {
+      case 0: ns_face_item<N, R, COMPACT, 0, 0>(a, op, E, q); break;
+      case 1: ns_face_item<N, R, COMPACT, 0, 1>(a, op, E, q); break;
+      case 2: ns_face_item<N, R, COMPACT, 1, 0>(a, op, E, q); break;
+      case 3: ns_face_item<N, R, COMPACT, 1, 1>(a, op, E, q); break;
+      case 4: ns_face_item<N, R, COMPACT, 2, 0>(a, op, E, q); break;
+      default: ns_face_item<N, R, COMPACT, 2, 1>(a, op, E, q); break;
     }
-    int base, stride;
-    line_of<3, N>(d, q, base, stride);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      if (m == d) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          int fv = (f * 5 + v) * NF + q;
-          R vown;
-          if constexpr (COMPACT) {
-            vown = thd * (E[SM::NO + fv] + op.kap[s] * Uh[v]);
-          } else {
-            const R *g = E + SM::G + (m * 5 + v) * NP + base;
-            R acc = R(0);
-#pragma unroll
-            for (int c = 0; c < N; ++c) acc += op.Lend[s][c] * g[c * stride];
-            vown = acc;
-          }
-          R voth = thd * (E[SM::NN + fv] + op.kap[so] * Uh[v]);
-          Vh[m * 5 + v] = s == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
-        }
-      } else {
-        int t3 = 3 - d - m;
-        int a_lo = q % N, a_hi = q / N;
-        int am = (m < t3) ? a_lo : a_hi, at = (m < t3) ? a_hi : a_lo;
-        int qs = (m < t3) ? at * N : at, qstep = (m < t3) ? 1 : N;
-        R thm = (R)a.two_over_h[m];
-        int e0i = edge_id(d, s, m, 0), e1i = edge_id(d, s, m, 1);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const R *g = E + SM::G + (m * 5 + v) * NP + base;
-          R vown = R(0);
-#pragma unroll
-          for (int c = 0; c < N; ++c) vown += op.Lend[s][c] * g[c * stride];
-          const R *tn = E + SM::TN + (f * 5 + v) * NF + qs;
-          R dT = R(0), eL = R(0), eR = R(0);
-#pragma unroll
-          for (int c = 0; c < N; ++c) {
-            R tv = tn[c * qstep];
-            dT += op.D[am][c] * tv;
-            eL += op.Lend[0][c] * tv;
-            eR += op.Lend[1][c] * tv;
-          }
-          R eLn = E[SM::E + (e0i * 5 + v) * N + at];
-          R eRn = E[SM::E + (e1i * 5 + v) * N + at];
-          R ehL = R(0.5) * (eLn + eL), ehR = R(0.5) * (eR + eRn);
-          R voth = thm * (dT + op.Mc[0][am] * (ehL - eL) + op.Mc[1][am] * (ehR - eR));
-          Vh[m * 5 + v] = s == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
-        }
-      }
-    }
-    R F[5];
-    face_flux<PHYS_NS, 5, R>(a, d, UL, UR, Uh, Vh, F);
-    R *Ew = sm + el * SM::TOTAL;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Ew[SM::FH + (f * 5 + v) * NF + q] = F[v];
   }
   __syncthreads();
-  // P4: one work item per line of each flux-point family
-  for (int t = tid; t < nb * 3 * NF; t += nth) {
-    int el = t / (3 * NF), r = t % (3 * NF);
-    int d = r / NF, q = r % NF, base, stride;
-    line_of<3, N>(d, q, base, stride);
+  // P4: interior fluxes and divergence, direction-major line items
+  for (int t = tid; t < 3 * epb * NF; t += nth) {
+    int d = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+    if (el >= nb) continue;
     R *E = sm + el * SM::TOTAL;
-    R ul[5][N], gl[15][N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) ul[v][c] = E[SM::U + v * NP + base + c * stride];
-#pragma unroll
-      for (int w = 0; w < 15; ++w) gl[w][c] = E[SM::G + w * NP + base + c * stride];
+    switch (d) {
+      case 0: ns_line_item<N, R, 0>(a, op, E, q); break;
+      case 1: ns_line_item<N, R, 1>(a, op, E, q); break;
+      default: ns_line_item<N, R, 2>(a, op, E, q); break;
     }
-    R Fl[N + 1][5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      Fl[0][v] = E[SM::FH + ((2 * d) * 5 + v) * NF + q];
-      Fl[N][v] = E[SM::FH + ((2 * d + 1) * 5 + v) * NF + q];
-    }
-#pragma unroll
-    for (int rr = 1; rr < N; ++rr) {
-      R Uf[5], Gf[15];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        R acc = R(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * ul[v][c];
-        Uf[v] = acc;
-      }
-#pragma unroll
-      for (int w = 0; w < 15; ++w) {
-        R acc = R(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * gl[w][c];
-        Gf[w] = acc;
-      }
-      interior_flux<PHYS_NS, 5, R>(a, d, Uf, Gf, Fl[rr]);
-    }
-    const R thd = (R)a.two_over_h[d];
-#pragma unroll
-    for (int ai = 0; ai < N; ++ai)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        R acc = R(0);
-#pragma unroll
-        for (int c = 0; c <= N; ++c) acc += op.M[ai][c] * Fl[c][v];
-        E[SM::RS + (d * 5 + v) * NP + base + ai * stride] = -thd * acc;
-      }
   }
   __syncthreads();
   // P5: sum of the three directional contributions
   for (int t = tid; t < nb * 5 * NP; t += nth) {
     int el = t / (5 * NP), r = t % (5 * NP);
     const R *E = sm + el * SM::TOTAL + SM::RS;
-    dudt[(long long)e0 * 5 * NP + t] = (double)E[r] + (double)E[5 * NP + r] + (double)E[10 * NP + r];
+    double Rv = (double)E[r] + (double)E[5 * NP + r] + (double)E[10 * NP + r];
+    long long i = (long long)e0 * 5 * NP + t;
+    if (ep.mode == 0) {
+      dudt[i] = Rv;
+    } else {
+      double accv = ep.first ? Rv : ep.acc[i] + ep.c * Rv;
+      if (ep.last) {
+        ep.out[i] = ep.u0[i] + ep.dt6 * accv;
+      } else {
+        ep.acc[i] = accv;
+        ep.out[i] = ep.u0[i] + ep.a * Rv;
+      }
+    }
   }
 }
 

@@ -21,6 +21,18 @@ struct NsConst {
         lam_over_mu((R)a.lam_over_mu), cp_over_pr((R)a.cp_over_pr), efix((R)a.efix), suth(a.suth) {}
 };
 
+// Reciprocal and square root: exact in FP64; the single-instruction
+// v_rcp_f32 / v_sqrt_f32 (about 1 ulp) in FP32, whose error sits far below
+// the FP32 path's tolerance.
+template <typename R>
+__device__ __forceinline__ R frcp(R x) { return R(1) / x; }
+template <>
+__device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R>
+__device__ __forceinline__ R fsqrt(R x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Component d of a 3-vector without runtime indexing of a private array
 // (which would put the array in scratch memory).
 template <typename R>
@@ -38,7 +50,7 @@ template <typename R>
 __device__ __forceinline__ Prim<R> ns_prim(const NsConst<R> &c, const R *U) {
   Prim<R> s;
   s.rho = c.rho0 + U[0];
-  s.inv = R(1) / s.rho;
+  s.inv = frcp(s.rho);
   s.u[0] = U[1] * s.inv;
   s.u[1] = U[2] * s.inv;
   s.u[2] = U[3] * s.inv;
@@ -76,7 +88,7 @@ __device__ __forceinline__ void ns_visc(const NsConst<R> &c, const Prim<R> &s, c
   R mu = c.mu0;
   if (c.suth) {
     R th = T * c.T0inv;
-    mu = c.mu0 * th * sqrt(th) * c.onepS / (th + c.S);
+    mu = c.mu0 * th * fsqrt(th) * c.onepS * frcp(th + c.S);
   }
   R lam = c.lam_over_mu * mu;
   R kappa = c.cp_over_pr * mu;
@@ -102,8 +114,8 @@ __device__ __forceinline__ void ns_roe(const NsConst<R> &c, const R *UL, const R
   R FL[5], FR[5];
   ns_conv(c, UL, L, d, FL);
   ns_conv(c, UR, Rr, d, FR);
-  R sL = sqrt(L.rho), sR = sqrt(Rr.rho);
-  R wsum = R(1) / (sL + sR);
+  R sL = fsqrt(L.rho), sR = fsqrt(Rr.rho);
+  R wsum = frcp(sL + sR);
   R HL = (L.rhoE + L.p) * L.inv, HR = (Rr.rhoE + Rr.p) * Rr.inv;
   R ut[3];
 #pragma unroll
@@ -112,21 +124,23 @@ __device__ __forceinline__ void ns_roe(const NsConst<R> &c, const R *UL, const R
   R rt = sL * sR;
   R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
   R c2 = c.gm1 * (Ht - R(0.5) * q2);
-  R cs = sqrt(c2);
+  R cs = fsqrt(c2);
   R un = pick(d, ut[0], ut[1], ut[2]);
   R du[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) du[i] = Rr.u[i] - L.u[i];
   R drho = Rr.rho - L.rho, dpj = Rr.dp - L.dp, dun = pick(d, du[0], du[1], du[2]);
-  R inv2c2 = R(0.5) / c2;
+  R ic2 = frcp(c2);
+  R inv2c2 = R(0.5) * ic2;
   R a1 = (dpj - rt * cs * dun) * inv2c2;
   R a5 = (dpj + rt * cs * dun) * inv2c2;
-  R a2 = drho - dpj / c2;
+  R a2 = drho - dpj * ic2;
   R l1 = fabs(un - cs), l2 = fabs(un), l5 = fabs(un + cs);
   R delta = c.efix * (l2 + cs);
   if (delta > R(0)) {
-    if (l1 < delta) l1 = (l1 * l1 + delta * delta) / (R(2) * delta);
-    if (l5 < delta) l5 = (l5 * l5 + delta * delta) / (R(2) * delta);
+    R i2d = R(0.5) * frcp(delta);
+    if (l1 < delta) l1 = (l1 * l1 + delta * delta) * i2d;
+    if (l5 < delta) l5 = (l5 * l5 + delta * delta) * i2d;
   }
   R dut[3];
 #pragma unroll
