@@ -1,0 +1,109 @@
+"""Pins of the closure-network reference and of the fine-to-coarse filter."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from paper_2608_09615_amd import workloads as W
+
+
+def test_bf16_round_matches_torch_and_ties_to_even():
+    rng = np.random.Generator(np.random.PCG64(0))
+    x = np.concatenate([rng.normal(size=1000) * 10.0 ** rng.integers(-5, 5, 1000),
+                        [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 0.0, 65504.0]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16_round(x), ref)
+    assert M.bf16_round(1.0 + 2 ** -8) == 1.0                      # tie -> even
+    assert M.bf16_round(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6        # tie -> even
+
+
+def test_gelu_matches_library_and_derivative():
+    z = np.linspace(-6, 6, 401)
+    ref = torch.nn.functional.gelu(torch.from_numpy(z), approximate="none").numpy()
+    assert np.abs(M.gelu(z) - ref).max() < 1e-15
+    h = 1e-6
+    fd = (M.gelu(z + h) - M.gelu(z - h)) / (2 * h)
+    assert np.abs(M.gelu_prime(z) - fd).max() < 1e-9
+
+
+def test_backward_matches_finite_differences():
+    n_in, n_h, n_out, B = 7, 5, 6, 4
+    p = M.init_params(n_in, n_h, n_out, seed=1)
+    rng = np.random.Generator(np.random.PCG64(2))
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(size=p[k].shape) * 0.1
+    x = rng.normal(size=(B, n_in))
+    t = rng.normal(size=(B, n_out))
+    y, cache = M.forward(p, x)
+    _, dy = M.mse(y, t)
+    g = M.flatten(M.backward(cache, dy))
+    flat = M.flatten(p)
+    h = 1e-6
+    fd = np.zeros_like(flat)
+    for i in range(flat.size):
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h
+        fm[i] -= h
+        lp = M.mse(M.forward(M.unflatten(fp, n_in, n_h, n_out), x)[0], t)[0]
+        lm = M.mse(M.forward(M.unflatten(fm, n_in, n_h, n_out), x)[0], t)[0]
+        fd[i] = (lp - lm) / (2 * h)
+    assert np.abs(g - fd).max() / np.abs(fd).max() < 1e-7
+
+
+def test_forward_matches_torch_mlp():
+    n_in, n_h, n_out = 11, 8, 9
+    p = M.init_params(n_in, n_h, n_out, seed=3)
+    x = np.random.Generator(np.random.PCG64(4)).normal(size=(5, n_in))
+    net = torch.nn.Sequential(torch.nn.Linear(n_in, n_h), torch.nn.GELU(), torch.nn.Linear(n_h, n_h),
+                              torch.nn.GELU(), torch.nn.Linear(n_h, n_out)).double()
+    with torch.no_grad():
+        for lin, (w, b) in zip([net[0], net[2], net[4]], [("W1", "b1"), ("W2", "b2"), ("W3", "b3")]):
+            lin.weight.copy_(torch.from_numpy(p[w]))
+            lin.bias.copy_(torch.from_numpy(p[b]))
+        ref = net(torch.from_numpy(x)).numpy()
+    assert np.abs(M.forward(p, x)[0] - ref).max() < 1e-13
+
+
+def test_adam_matches_torch():
+    rng = np.random.Generator(np.random.PCG64(5))
+    p0 = rng.normal(size=17)
+    w = torch.nn.Parameter(torch.from_numpy(p0.copy()))
+    opt = torch.optim.Adam([w], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(17), np.zeros(17)
+    for t in range(1, 6):
+        g = rng.normal(size=17)
+        w.grad = torch.from_numpy(g.copy())
+        opt.step()
+        p, m, v = M.adam(p, g, m, v, t, lr=1e-2)
+    assert np.abs(p - w.detach().numpy()).max() < 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_filter_reproduces_coarse_polynomials(p):
+    """Sampling a degree-p polynomial (per coordinate) on the fine mesh and
+    projecting returns its values at the coarse points exactly."""
+    r, nelc = 4, (2, 3, 2)
+    nelf = tuple(r * c for c in nelc)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.5, 2.0)
+    Xf, Yf, Zf = W.points_3d(nelf, lo, hi, p)
+    Xc, Yc, Zc = W.points_3d(nelc, lo, hi, p)
+    # a polynomial of degree p in each coordinate, different on every coarse
+    # element would be exact too; a global one suffices here
+    f = lambda X, Y, Z: (1 + X ** p - 0.5 * X) * (2 - Y ** p) * (0.3 + Z ** p + Z)
+    Uc = M.filter_state(f(Xf, Yf, Zf)[:, None], nelf, p, r)
+    assert np.abs(Uc[:, 0] - f(Xc, Yc, Zc)).max() < 1e-12
+
+
+def test_filter_preserves_integrals():
+    p, r, nelc = 3, 4, (2, 2, 3)
+    nelf = tuple(r * c for c in nelc)
+    rng = np.random.Generator(np.random.PCG64(6))
+    Uf = rng.normal(size=(np.prod(nelf), 2, p + 1, p + 1, p + 1))
+    Uc = M.filter_state(Uf, nelf, p, r)
+    _, ws = np.polynomial.legendre.leggauss(p + 1)
+    w3 = ws[:, None, None] * ws[None, :, None] * ws[None, None, :]
+    If = np.einsum("evkji,kji->v", Uf, w3) / r ** 3
+    Ic = np.einsum("evkji,kji->v", Uc, w3)
+    assert np.abs(If - Ic).max() < 1e-12 * np.abs(Uf).sum()
