@@ -1,0 +1,86 @@
+/*
+ * sd_closure.h - C ABI of the learned per-element closure of the SD
+ * right-hand side (an MLP that corrects the coarse-grid residual) and of the
+ * fine-to-coarse filter that builds its training data.
+ *
+ * Network: y = W3 g(W2 g(W1 x + b1) + b2) + b3, g the exact-erf GELU.
+ * Parameters live in one flat FP32 vector P (the master copy), in the order
+ * W1 [n_hidden][n_in], b1 [n_hidden], W2 [n_hidden][n_hidden], b2,
+ * W3 [n_out][n_hidden], b3 [n_out]; weights row-major [out][in].  The
+ * products use a BF16 copy of P (Wb, same length and offsets, weights only
+ * read) on BF16 matrix cores with FP32 accumulation; every layer input is
+ * rounded to BF16 (round to nearest even) before its product.  Sizes n_in,
+ * n_hidden, n_out must be multiples of 16.
+ *
+ * All pointers are device pointers owned by the caller; every call is
+ * enqueued on the given hipStream_t (NULL = default stream) and returns
+ * SD_OK or a negative code of sd.h (message via sd_last_error()).
+ */
+#ifndef SD_CLOSURE_H
+#define SD_CLOSURE_H
+
+#include <stdint.h>
+
+#include "sd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n_in, n_hidden, n_out;
+} sd_mlp_shape;
+
+/* Number of FP32 values of P (and of BF16 values of Wb). */
+long long sd_mlp_param_count(const sd_mlp_shape *shape);
+
+/* Bytes of the activation workspace for a batch of B samples (kept between
+ * sd_mlp_forward and sd_mlp_backward). */
+long long sd_mlp_work_bytes(const sd_mlp_shape *shape, int batch);
+
+/* Wb = bf16(P), round to nearest even. */
+int sd_mlp_round_weights(const sd_mlp_shape *shape, const float *P, uint16_t *Wb, void *stream);
+
+/* Y [B][n_out] = net(X [B][n_in]); the activations go to work. */
+int sd_mlp_forward(const sd_mlp_shape *shape, const float *P, const uint16_t *Wb, const float *X, int batch,
+                   float *Y, void *work, void *stream);
+
+/* Grad [param_count] = d(sum dY . Y)/dP for the forward pass whose
+ * activations are in work (weights as their BF16 values, the roundings of
+ * the forward pass treated as fixed); products in FP32. */
+int sd_mlp_backward(const sd_mlp_shape *shape, const uint16_t *Wb, void *work, const float *dY, int batch,
+                    float *grad, void *stream);
+
+/* Mean square error of Y against T (n values): dY = 2 (Y - T) / n and the
+ * loss into *loss (device FP64 scalar); deterministic reduction. */
+int sd_mse(const float *Y, const float *T, long long n, float *dY, double *loss, void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on P with moments
+ * m, v (FP32, same length), then Wb = bf16(P). */
+int sd_mlp_adam(const sd_mlp_shape *shape, float *P, uint16_t *Wb, const float *grad, float *m, float *v,
+                int step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* L2 projection of a fine degree-p state on nel_fine[0..2] periodic-box
+ * elements onto the degree-p space of each coarse element (ratio^3 fine
+ * elements each), evaluated at the coarse solution points.  Layout of both
+ * states as in sd.h (u[e][v][k][j][i]); nel_fine[d] must be divisible by
+ * ratio; ratio * (p + 1) <= 16 and p + 1 <= 8. */
+int sd_filter(const double *fine, const int *nel_fine, int ratio, int p, int nv, double *coarse, void *stream);
+
+/* Closure of an SD context (3-D Navier-Stokes): every later right-hand side
+ * (sd_rhs, and each stage of sd_rk_step) adds to element e
+ *     C_e = out_scale[v] * net((u_e[v] - in_shift[v]) / in_scale[v])
+ * unless C_e holds a non-finite value or max|C_e| > max|R_e| (then C_e = 0
+ * for that element).  n_in = n_out = 5 (p+1)^3.  P and Wb stay owned by the
+ * caller and are read at each evaluation.  P = NULL switches the closure off. */
+int sd_closure_set(sd_ctx *ctx, const sd_mlp_shape *shape, const float *P, const uint16_t *Wb,
+                   const float *in_shift, const float *in_scale, const float *out_scale);
+
+/* Number of element corrections discarded since the last sd_closure_set
+ * (waits for the context's stream). */
+int sd_closure_rejected(sd_ctx *ctx, long long *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SD_CLOSURE_H */

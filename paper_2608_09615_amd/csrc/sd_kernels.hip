@@ -468,4 +468,6 @@ __global__ void k_diag_final(const double *__restrict__ part, int nparts, double
 }  // namespace sd
 
 #include "sd_ns_kernel.h"
+#include "sd_mlp.h"
 #include "sd_dispatch.inc"
+#include "sd_closure.inc"

@@ -1,0 +1,237 @@
+// Kernels of the learned closure: a dense MLP with exact-erf GELU, forward on
+// BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation),
+// backward in FP32, MSE, Adam; and the fine-to-coarse L2 projection filter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sd {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x0040u);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// x (FP32) -> bf16
+__global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// One dense layer Z = X W^T + b on matrix cores; X [M][K] bf16, W [N][K] bf16
+// (row-major), b [N] FP32; K and N multiples of 16.  One wavefront per 16x16
+// tile of Z.  Operand layout of the 16x16x16 BF16 instruction: lane l holds
+// row l%16 of the A tile and column l%16 of the B tile at k = 4(l/16)+0..3,
+// and D[4(l/16)+j][l%16] of the result.  ACT: also A_out = bf16(gelu(Z)).
+template <bool ACT>
+__global__ void __launch_bounds__(256) k_dense_fwd(const uint16_t *__restrict__ X, const uint16_t *__restrict__ W,
+                                                   const float *__restrict__ bias, int M, int N, int K,
+                                                   float *__restrict__ Z, uint16_t *__restrict__ Aout) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ntn = N / 16;
+  const int mt = wave / ntn, nt = wave % ntn;
+  if (mt * 16 >= M) return;                     // uniform for the wavefront
+  const int r = lane & 15, kq = lane >> 4;
+  const int row = mt * 16 + r, col = nt * 16 + r;
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4_t a = {0, 0, 0, 0};
+    if (row < M) a = *reinterpret_cast<const bf16x4_t *>(X + (long long)row * K + k0 + 4 * kq);
+    bf16x4_t b = *reinterpret_cast<const bf16x4_t *>(W + (long long)col * K + k0 + 4 * kq);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int m = mt * 16 + 4 * kq + j;
+    if (m < M) {
+      float z = acc[j] + bias[col];
+      Z[(long long)m * N + col] = z;
+      if constexpr (ACT) Aout[(long long)m * N + col] = to_bf16(gelu_f(z));
+    }
+  }
+}
+
+// C [M][N] = sum_k A(m, k) B(k, n) in FP32 with strided operands; 32x32
+// output tile per block of 256 threads, 2x2 outputs per thread.
+template <typename TA, typename TB>
+__device__ __forceinline__ float ld_as_f32(const TA *p) {
+  if constexpr (sizeof(TA) == 2) return from_bf16(*reinterpret_cast<const uint16_t *>(p));
+  else return *p;
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) k_gemm_f32(int M, int N, int K, const TA *__restrict__ A, long long sam,
+                                                  long long sak, const TB *__restrict__ B, long long sbk,
+                                                  long long sbn, float *__restrict__ C) {
+  __shared__ float As[32][33];
+  __shared__ float Bs[32][33];
+  const int tid = threadIdx.x;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int ty = tid / 16, tx = tid % 16;
+  float c00 = 0.f, c01 = 0.f, c10 = 0.f, c11 = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int idx = tid; idx < 1024; idx += 256) {
+      // fast index along the unit-stride dimension of each operand
+      int i, kk;
+      if (sam == 1) { i = idx % 32; kk = idx / 32; } else { kk = idx % 32; i = idx / 32; }
+      int m = m0 + i, k = k0 + kk;
+      As[i][kk] = (m < M && k < K) ? ld_as_f32<TA, TB>(A + m * sam + k * sak) : 0.f;
+      int jj, kb;
+      if (sbn == 1) { jj = idx % 32; kb = idx / 32; } else { kb = idx % 32; jj = idx / 32; }
+      int n = n0 + jj, k2 = k0 + kb;
+      Bs[kb][jj] = (n < N && k2 < K) ? ld_as_f32<TB, TA>(B + k2 * sbk + n * sbn) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      float a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
+      float b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
+      c00 += a0 * b0; c01 += a0 * b1; c10 += a1 * b0; c11 += a1 * b1;
+    }
+    __syncthreads();
+  }
+  int m = m0 + 2 * ty, n = n0 + 2 * tx;
+  if (m < M && n < N) C[(long long)m * N + n] = c00;
+  if (m < M && n + 1 < N) C[(long long)m * N + n + 1] = c01;
+  if (m + 1 < M && n < N) C[(long long)(m + 1) * N + n] = c10;
+  if (m + 1 < M && n + 1 < N) C[(long long)(m + 1) * N + n + 1] = c11;
+}
+
+// g <- g * gelu'(z)
+__global__ void k_gelu_bwd(float *__restrict__ g, const float *__restrict__ z, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] *= gelu_prime_f(z[i]);
+}
+
+// out[n] = sum_b x[b][n], one thread per column, fixed order
+__global__ void k_colsum(const float *__restrict__ x, int B, int N, float *__restrict__ out) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += x[(long long)b * N + n];
+  out[n] = s;
+}
+
+// dY = 2 (Y - T) / n and per-block partial sums of (Y - T)^2
+__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ Y, const float *__restrict__ T, long long n,
+                                             float *__restrict__ dY, double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const float scale = 2.0f / (float)n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float d = Y[i] - T[i];
+    dY[i] = scale * d;
+    acc += (double)d * (double)d;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const double *__restrict__ part, int nparts, double inv_n, double *__restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    *out = s * inv_n;
+  }
+}
+
+// Adam step with bias corrections c1 = 1/(1-b1^t), c2 = 1/(1-b2^t); Wb = bf16(P)
+__global__ void k_adam(float *__restrict__ P, uint16_t *__restrict__ Wb, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float p = P[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  P[i] = p;
+  Wb[i] = to_bf16(p);
+}
+
+// Fine-to-coarse L2 projection: one block per (coarse element, variable).
+constexpr int kFilterMaxRN = 16;
+constexpr int kFilterMaxN = 8;
+struct FilterArgs {
+  int nelc[3];
+  int nelf[3];
+  int ratio, n, nv;
+  double P[kFilterMaxN * kFilterMaxRN];   // [n][ratio*n], coarse coefficient from fine values
+};
+
+__global__ void __launch_bounds__(256) k_filter(const double *__restrict__ fine, double *__restrict__ coarse,
+                                                FilterArgs a) {
+  __shared__ double F[kFilterMaxRN * kFilterMaxRN * kFilterMaxRN];
+  __shared__ double T1[kFilterMaxRN * kFilterMaxRN * kFilterMaxN];
+  __shared__ double T2[kFilterMaxRN * kFilterMaxN * kFilterMaxN];
+  const int n = a.n, r = a.ratio, rn = r * n, nv = a.nv;
+  const int ec = blockIdx.x / nv, v = blockIdx.x % nv;
+  const int cx = ec % a.nelc[0], cy = (ec / a.nelc[0]) % a.nelc[1], cz = ec / (a.nelc[0] * a.nelc[1]);
+  const int n3 = n * n * n;
+  // F[gz][gy][gx] over the r^3 fine elements of this coarse element
+  for (int t = threadIdx.x; t < r * r * r * n3; t += blockDim.x) {
+    int fe = t / n3, pt = t % n3;
+    int fx = fe % r, fy = (fe / r) % r, fz = fe / (r * r);
+    int i = pt % n, j = (pt / n) % n, k = pt / (n * n);
+    long long ef = (long long)(cx * r + fx) + (long long)a.nelf[0] * ((cy * r + fy) + (long long)a.nelf[1] * (cz * r + fz));
+    F[((fz * n + k) * rn + (fy * n + j)) * rn + (fx * n + i)] = fine[(ef * nv + v) * n3 + pt];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < rn * rn * n; t += blockDim.x) {       // along x
+    int ic = t % n, gy = (t / n) % rn, gz = t / (n * rn);
+    double s = 0.0;
+    for (int g = 0; g < rn; ++g) s += a.P[ic * rn + g] * F[(gz * rn + gy) * rn + g];
+    T1[(gz * rn + gy) * n + ic] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < rn * n * n; t += blockDim.x) {        // along y
+    int ic = t % n, jc = (t / n) % n, gz = t / (n * n);
+    double s = 0.0;
+    for (int g = 0; g < rn; ++g) s += a.P[jc * rn + g] * T1[(gz * rn + g) * n + ic];
+    T2[(gz * n + jc) * n + ic] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n3; t += blockDim.x) {               // along z
+    int ic = t % n, jc = (t / n) % n, kc = t / (n * n);
+    double s = 0.0;
+    for (int g = 0; g < rn; ++g) s += a.P[kc * rn + g] * T2[(g * n + jc) * n + ic];
+    coarse[((long long)ec * nv + v) * n3 + t] = s;
+  }
+}
+
+// Closure input: X[e][v n^3 + pt] = (u[e][v][pt] - shift[v]) / scale[v]
+struct ClosureNorm {
+  float shift[5], scale[5], out_scale[5];
+};
+
+__global__ void k_closure_input(const double *__restrict__ u, float *__restrict__ X, long long n, int np,
+                                ClosureNorm cn) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int v = (int)((i / np) % 5);
+  X[i] = (float)((u[i] - (double)cn.shift[v]) / (double)cn.scale[v]);
+}
+
+}  // namespace sd

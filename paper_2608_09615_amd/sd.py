@@ -16,7 +16,9 @@ PHYSICS = {"diffusion": 0, "pme": 1, "ns": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
-           "sd_rk_step", "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_last_error"]
+           "sd_rk_step", "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_last_error",
+           "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
+           "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"]
 
 
 class SDError(RuntimeError):
@@ -50,6 +52,10 @@ class Params(ctypes.Structure):
     ]
 
 
+class MlpShape(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int), ("n_hidden", ctypes.c_int), ("n_out", ctypes.c_int)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("ke", ctypes.c_double), ("enstrophy", ctypes.c_double), ("mass", ctypes.c_double),
                 ("mom", ctypes.c_double * 3), ("energy", ctypes.c_double), ("umax", ctypes.c_double),
@@ -81,10 +87,26 @@ def load_library(path=LIB_PATH):
     L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
     L.sd_timing.argtypes = [vp, ctypes.c_int]
     L.sd_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    sp = ctypes.POINTER(MlpShape)
+    L.sd_mlp_param_count.argtypes = [sp]
+    L.sd_mlp_param_count.restype = ctypes.c_longlong
+    L.sd_mlp_work_bytes.argtypes = [sp, ctypes.c_int]
+    L.sd_mlp_work_bytes.restype = ctypes.c_longlong
+    L.sd_mlp_round_weights.argtypes = [sp, vp, vp, vp]
+    L.sd_mlp_forward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.sd_mlp_backward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp]
+    L.sd_mse.argtypes = [vp, vp, ctypes.c_longlong, vp, vp, vp]
+    L.sd_mlp_adam.argtypes = [sp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, vp]
+    L.sd_filter.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+    L.sd_closure_set.argtypes = [vp, sp, vp, vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(ctypes.c_float)]
+    L.sd_closure_rejected.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
-              "sd_diagnostics", "sd_timing", "sd_timing_read"):
+              "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_mlp_round_weights", "sd_mlp_forward",
+              "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -187,6 +209,23 @@ class SD:
         _check(load_library().sd_timing_read(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
 
+    def closure_set(self, mlp, in_shift, in_scale, out_scale):
+        """Add the network ``mlp`` (an :class:`Mlp`) as a per-element closure;
+        ``mlp=None`` switches it off."""
+        f5 = ctypes.c_float * 5
+        if mlp is None:
+            _check(load_library().sd_closure_set(self._ctx, None, None, None, None, None, None))
+            self._closure = None
+            return
+        self._closure = mlp
+        _check(load_library().sd_closure_set(self._ctx, ctypes.byref(mlp.shape), _ptr(mlp.P), _ptr(mlp.Wb),
+                                             f5(*in_shift), f5(*in_scale), f5(*out_scale)))
+
+    def closure_rejected(self):
+        n = ctypes.c_longlong()
+        _check(load_library().sd_closure_rejected(self._ctx, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             load_library().sd_free(self._ctx)
@@ -197,3 +236,84 @@ class SD:
             self.close()
         except Exception:
             pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mlp:
+    """Closure network n_in -> n_hidden -> n_hidden -> n_out (GELU) with FP32
+    master parameters ``P`` and their BF16 copy ``Wb`` (device tensors)."""
+
+    def __init__(self, n_in, n_hidden, n_out, P=None):
+        import torch
+        self.shape = MlpShape(n_in, n_hidden, n_out)
+        L = load_library()
+        self.nparams = L.sd_mlp_param_count(ctypes.byref(self.shape))
+        if self.nparams < 0:
+            raise SDError(SD_EINVAL, L.sd_last_error().decode())
+        self.P = torch.zeros(self.nparams, dtype=torch.float32, device="cuda") if P is None else P
+        self.Wb = torch.zeros(self.nparams, dtype=torch.int16, device="cuda")
+        self.m = torch.zeros_like(self.P)
+        self.v = torch.zeros_like(self.P)
+        self.grad = torch.zeros_like(self.P)
+        self.step = 0
+        self._work = None
+        self._wbatch = 0
+        self.round_weights()
+
+    def round_weights(self):
+        _check(load_library().sd_mlp_round_weights(ctypes.byref(self.shape), _ptr(self.P), _ptr(self.Wb),
+                                                   _stream()))
+
+    def work(self, batch):
+        import torch
+        if batch > self._wbatch:
+            nb = load_library().sd_mlp_work_bytes(ctypes.byref(self.shape), batch)
+            self._work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            self._wbatch = batch
+        return self._work
+
+    def forward(self, X, Y=None):
+        import torch
+        B = X.shape[0]
+        if Y is None:
+            Y = torch.empty((B, self.shape.n_out), dtype=torch.float32, device="cuda")
+        _check(load_library().sd_mlp_forward(ctypes.byref(self.shape), _ptr(self.P), _ptr(self.Wb), _ptr(X), B,
+                                             _ptr(Y), _ptr(self.work(B)), _stream()))
+        return Y
+
+    def backward(self, dY):
+        B = dY.shape[0]
+        _check(load_library().sd_mlp_backward(ctypes.byref(self.shape), _ptr(self.Wb), _ptr(self.work(B)),
+                                              _ptr(dY), B, _ptr(self.grad), _stream()))
+        return self.grad
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(load_library().sd_mlp_adam(ctypes.byref(self.shape), _ptr(self.P), _ptr(self.Wb), _ptr(self.grad),
+                                          _ptr(self.m), _ptr(self.v), self.step, lr, beta1, beta2, eps,
+                                          _stream()))
+
+
+def mse(Y, T, dY, loss):
+    """dY = 2 (Y - T) / n and loss (one-element FP64 device tensor)."""
+    _check(load_library().sd_mse(_ptr(Y), _ptr(T), Y.numel(), _ptr(dY), _ptr(loss), _stream()))
+
+
+def filter_state(fine, nel_fine, ratio, p, nv):
+    """L2 projection of a fine state onto the coarse elements (device tensors)."""
+    import torch
+    nec = 1
+    for d in range(3):
+        nec *= nel_fine[d] // ratio
+    out = torch.empty((nec, nv) + (p + 1,) * 3, dtype=torch.float64, device="cuda")
+    nel = (ctypes.c_int * 3)(*nel_fine)
+    _check(load_library().sd_filter(_ptr(fine), nel, ratio, p, nv, _ptr(out), _stream()))
+    return out

@@ -1,0 +1,158 @@
+"""GPU closure kernels against the FP64 reference (oracle/mlp.py): BF16-MFMA
+forward, FP32 backward, MSE, Adam, the fine-to-coarse filter, and the
+closure inside the solver (correction and per-element fallback)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2608_09615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_net(torch, n_in, n_h, n_out, seed, bias=0.1):
+    from paper_2608_09615_amd.sd import Mlp
+    p = M.init_params(n_in, n_h, n_out, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(size=p[k].shape) * bias
+    flat = M.flatten(p).astype(np.float32)
+    net = Mlp(n_in, n_h, n_out, P=torch.from_numpy(flat).to("cuda"))
+    # the reference uses exactly the FP32 master values the GPU holds
+    return net, M.unflatten(flat.astype(np.float64), n_in, n_h, n_out)
+
+
+@pytest.mark.parametrize("shape,B", [((64, 32, 48), 100), ((320, 128, 320), 1000)])
+def test_mlp_forward_matches_reference(torch_cuda, shape, B):
+    print(f"[mlp fwd] {shape} B={B}", flush=True)
+    net, p = make_net(torch_cuda, *shape, seed=1)
+    x = np.random.Generator(np.random.PCG64(2)).normal(size=(B, shape[0])).astype(np.float32)
+    y = net.forward(torch_cuda.from_numpy(x).to("cuda")).cpu().numpy().astype(np.float64)
+    yo, _ = M.forward(p, x.astype(np.float64), bf16=True)
+    err = np.abs(y - yo)
+    scale = np.abs(yo).max()
+    # products differ by FP32 accumulation only; a BF16 rounding of an
+    # activation taken on the other side of a tie may move a few outputs
+    assert np.mean(err < 1e-4 * scale) > 0.999
+    assert err.max() < 2e-2 * scale
+
+
+@pytest.mark.parametrize("shape,B", [((64, 32, 48), 100), ((320, 128, 320), 512)])
+def test_mlp_backward_matches_reference(torch_cuda, shape, B):
+    print(f"[mlp bwd] {shape} B={B}", flush=True)
+    net, p = make_net(torch_cuda, *shape, seed=3)
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.normal(size=(B, shape[0])).astype(np.float32)
+    dy = (rng.normal(size=(B, shape[2])) / B).astype(np.float32)
+    net.forward(torch_cuda.from_numpy(x).to("cuda"))
+    g = net.backward(torch_cuda.from_numpy(dy).to("cuda")).cpu().numpy().astype(np.float64)
+    _, cache = M.forward(p, x.astype(np.float64), bf16=True)
+    go = M.flatten(M.backward(cache, dy.astype(np.float64)))
+    assert np.abs(g - go).max() < 1e-3 * np.abs(go).max()
+    assert np.linalg.norm(g - go) < 1e-4 * np.linalg.norm(go)
+
+
+def test_mse_and_adam(torch_cuda):
+    torch = torch_cuda
+    from paper_2608_09615_amd.sd import mse
+    rng = np.random.Generator(np.random.PCG64(5))
+    y = rng.normal(size=(37, 48)).astype(np.float32)
+    t = rng.normal(size=(37, 48)).astype(np.float32)
+    dY = torch.empty((37, 48), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mse(torch.from_numpy(y).to("cuda"), torch.from_numpy(t).to("cuda"), dY, loss)
+    lo, go = M.mse(y.astype(np.float64), t.astype(np.float64))
+    assert abs(loss.item() - lo) < 1e-6 * lo          # Y - T is formed in FP32
+    assert np.abs(dY.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+    net, p = make_net(torch, 64, 32, 48, seed=6)
+    P0 = M.flatten(p)
+    m = np.zeros_like(P0)
+    v = np.zeros_like(P0)
+    Po = P0.copy()
+    for step in range(1, 4):
+        g = rng.normal(size=P0.size).astype(np.float32)
+        net.grad.copy_(torch.from_numpy(g))
+        net.adam(1e-2)
+        Po, m, v = M.adam(Po, g.astype(np.float64), m, v, step, lr=1e-2)
+    P = net.P.cpu().numpy()
+    assert np.abs(P - Po).max() < 1e-5
+    Wb = net.Wb.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(Wb.astype(np.uint32).view(np.float32).astype(np.float64), M.bf16_round(P))
+
+
+@pytest.mark.parametrize("ratio,p,nelc", [(4, 3, (2, 3, 1)), (2, 2, (3, 2, 2)), (4, 1, (1, 1, 2))])
+def test_filter_matches_reference(torch_cuda, ratio, p, nelc):
+    from paper_2608_09615_amd.sd import filter_state
+    nelf = tuple(ratio * c for c in nelc)
+    Uf = np.random.Generator(np.random.PCG64(7)).normal(size=(int(np.prod(nelf)), 5, p + 1, p + 1, p + 1))
+    Uc = filter_state(torch_cuda.from_numpy(Uf).to("cuda"), nelf, ratio, p, 5).cpu().numpy()
+    Uo = M.filter_state(Uf, nelf, p, ratio)
+    assert np.abs(Uc - Uo).max() < 1e-13 * np.abs(Uo).max()
+
+
+def test_closure_in_solver(torch_cuda, oracle_lib):
+    """R_closure = R_plain + out_scale * net(normalised u) per element, and a
+    correction larger than R is discarded for that element."""
+    torch = torch_cuda
+    from paper_2608_09615_amd import SD
+    nel, p = (3, 2, 2), 3
+    lo, hi = W.tgv_domain()
+    U = W.perturbed_tgv_state(nel, p, seed=11, noise=1e-3)
+    nve = 5 * 64
+    net, prm = make_net(torch, nve, 32, nve, seed=8, bias=0.0)
+    shift = [1.0, 0.0, 0.0, 0.0, 178.57]
+    scale = [0.01, 0.5, 0.5, 0.5, 0.2]
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, "compact", oracle_lib.make_params("ns"))
+    X = ((U.reshape(len(U), 5, -1) - np.array(shift)[None, :, None]) / np.array(scale)[None, :, None])
+    X = X.reshape(len(U), nve).astype(np.float32).astype(np.float64)
+    Yo, _ = M.forward(prm, X, bf16=True)
+    for out_scale, expect_use in ((1e-3, True), (1e3, False)):
+        sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+        sd.closure_set(net, shift, scale, [out_scale] * 5)
+        u = torch.from_numpy(U).to("cuda")
+        R = sd.rhs(u).cpu().numpy()
+        C = (Yo * out_scale).reshape(Ro.shape)
+        rej = sd.closure_rejected()
+        if expect_use:
+            assert rej == 0
+            ref = Ro + C
+        else:
+            assert rej == len(U)
+            ref = Ro
+        # same bar as the forward test: BF16 roundings of activations may fall
+        # on the other side of a tie for a few values
+        d = np.abs(R - ref)
+        assert d.max() < 2e-2 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()
+        assert np.mean(d < 1e-4 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()) > 0.999
+        sd.close()
+
+
+def test_training_reduces_loss(torch_cuda):
+    """A few hundred Adam steps of the GPU forward/backward kernels fit a
+    smooth target."""
+    torch = torch_cuda
+    from paper_2608_09615_amd.sd import mse
+    net, _ = make_net(torch, 64, 64, 64, seed=9, bias=0.0)
+    rng = np.random.Generator(np.random.PCG64(10))
+    X = rng.normal(size=(512, 64)).astype(np.float32)
+    T = np.tanh(X[:, ::-1] * 0.5).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).to("cuda"), torch.from_numpy(T).to("cuda")
+    dY = torch.empty_like(Td)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    losses = []
+    for it in range(300):
+        Y = net.forward(Xd)
+        mse(Y, Td, dY, loss)
+        net.backward(dY)
+        net.adam(3e-3)
+        if it % 50 == 0 or it == 299:
+            losses.append(loss.item())
+    assert losses[-1] < 0.1 * losses[0]

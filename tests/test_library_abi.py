@@ -7,13 +7,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sd.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sd_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(sd_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -33,8 +36,18 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_binding_names_match_header():
     from paper_2608_09615_amd import sd
-    assert sorted(sd.EXPORTS) == sorted(n for n in declared_functions() if n in sd.EXPORTS)
-    assert set(sd.EXPORTS) <= set(declared_functions())
+    assert set(sd.EXPORTS) == set(declared_functions())
+
+
+def test_mlp_shape_validation(lib):
+    from paper_2608_09615_amd import sd
+    good = sd.MlpShape(320, 128, 320)
+    assert lib.sd_mlp_param_count(ctypes.byref(good)) == 98880
+    assert lib.sd_mlp_work_bytes(ctypes.byref(good), 4096) > 0
+    bad = sd.MlpShape(320, 100, 320)
+    assert lib.sd_mlp_param_count(ctypes.byref(bad)) == -1
+    assert lib.sd_mlp_forward(ctypes.byref(bad), None, None, None, 1, None, None, None) == -1
+    assert lib.sd_filter(None, None, 4, 3, 5, None, None) == -1
 
 
 def _init(lib, dim=3, nel=(4, 4, 4), p=3, scheme=1, **kw):
