@@ -8,18 +8,24 @@
 //       staged in LDS with vector loads;
 //   P2  auxiliary gradient at the solution points (15 components); the own
 //       face traces it needs come from the same state values;
-//   P3  one work item per face point: own trace (and, compact, normal-gradient
-//       trace) from the state, the common gradient (own side from the
-//       gradient, neighbour side rebuilt from its traces and the edge traces)
-//       and the interface flux (Roe minus viscous), kept in LDS;
-//   P4  one work item per line of a flux-point family: the line's state and
-//       gradient in registers, the n-1 interior fluxes, the two interface
-//       fluxes, and the divergence along the line (-2/h_d M F);
-//   P5  the three directional contributions summed and stored in FP64.
-// Work items of P3 and P4 are ordered face-major (direction-major for
-// P4) so that, with epb * n^2 = 64 (p = 3, four elements per block), every
-// wavefront works on a single face direction: the bodies are compiled per
-// direction and the direction branches are uniform.
+//   P3  one work item per face point, two passes: own trace (and, compact,
+//       normal-gradient trace) from the state, the common gradient (own side
+//       from the gradient, neighbour side rebuilt from its traces and the
+//       edge traces) and minus the viscous flux; then the Roe flux of the two
+//       traces added; kept in LDS;
+//   P4  one work item per interior flux point of a family: the 20 state and
+//       gradient values interpolated along its line and the interior flux,
+//       kept in LDS over the dead neighbour traces;
+//   P5  one work item per line and variable: the divergence along the line
+//       (-2/h_d M F over the n+1 fluxes), kept in LDS over the dead gradient;
+//       then per value the three directional contributions summed in FP64
+//       (and the RK stage applied).
+// Work items of P2-P4 are ordered direction-major (face-major for P3) so
+// that, with epb * n^2 = 64 (p = 3, four elements per block), every
+// wavefront works on a single direction (and, in P4, a single flux point of
+// the line): the bodies are compiled per direction and the branches are
+// uniform.  Small work items keep the register footprint low, so that more
+// wavefronts share a compute unit.
 #pragma once
 
 #include <type_traits>
@@ -30,6 +36,14 @@
 namespace sd {
 
 constexpr int kNsMaxEpb = 8;
+
+// Largest block of k_rhs_ns: 512 threads where the face pass fits in 128
+// VGPR-pairs' worth of registers per lane, 256 where FP64 at n >= 5 needs
+// the whole register file of a lane (one wavefront per SIMD).
+template <int N, typename R>
+__host__ __device__ constexpr int ns_max_threads() {
+  return (sizeof(R) == 8 && N >= 5) ? 256 : 512;
+}
 
 template <int N, typename R>
 struct NsOps {
@@ -48,14 +62,15 @@ template <int N>
 struct NsSmem {
   static constexpr int NP = N * N * N, NF = N * N;
   static constexpr int U = 0;                        // [5][NP]
-  static constexpr int G = pad4(U + 5 * NP);         // [3][5][NP]
+  static constexpr int G = pad4(U + 5 * NP);         // [3][5][NP]; P5: directional residuals
   static constexpr int TNN = pad4(G + 15 * NP);      // [6][10][NF] neighbour T (v < 5) and NN (v >= 5)
   static constexpr int E = pad4(TNN + 60 * NF);      // [12][5][N] edge-neighbour edge traces
   static constexpr int FH = pad4(E + 60 * N);        // [6][5][NF] interface fluxes
   static constexpr int END = pad4(FH + 30 * NF);
-  // [3][5][NP] partial residuals: alias TNN..E (dead after P3) when they fit
-  static constexpr int RS = (TNN + 15 * NP <= FH) ? TNN : END;
-  static constexpr int TOTAL = (RS == TNN) ? END : pad4(END + 15 * NP);
+  // [3][N-1][NF][5] interior fluxes: alias TNN..E (dead after P3) when they fit
+  static constexpr int FIN = 15 * NF * (N - 1);
+  static constexpr int FI = (TNN + FIN <= FH) ? TNN : END;
+  static constexpr int TOTAL = (FI == TNN) ? END : pad4(END + FIN);
 };
 
 // number of values moved per vector load for a contiguous run of CNT values
@@ -72,8 +87,11 @@ template <> struct VecT<float, 1> { using T = float; };
 template <> struct VecT<double, 2> { using T = double2; };
 template <> struct VecT<double, 1> { using T = double; };
 
-// interface flux at face point q of face (D, S)
-template <int N, typename R, bool COMPACT, int D, int S>
+// interface flux at face point q of face (D, S), in two passes over the face
+// points: PART 0 stores minus the viscous flux of the common solution and
+// gradient, PART 1 adds the Roe flux of the two traces.  Each pass keeps only
+// its own operands live.
+template <int N, typename R, bool COMPACT, int D, int S, int PART>
 __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q) {
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF, f = 2 * D + S, SO = 1 - S;
@@ -97,6 +115,14 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
     UL[v] = S == 0 ? oth : own;
     UR[v] = S == 0 ? own : oth;
     Uh[v] = S == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
+  }
+  NsConst<R> c(a);
+  R F[5];
+  if constexpr (PART == 1) {
+    ns_roe(c, UL, UR, D, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) E[SM::FH + (f * 5 + v) * NF + q] += F[v];
+    return;
   }
   // normal component: one-sided (compact) or standard (BR1) on each side
 #pragma unroll
@@ -146,62 +172,72 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
       Vh[m * 5 + v] = S == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
     }
   }
-  R F[5];
-  face_flux<PHYS_NS, 5, R>(a, D, UL, UR, Uh, Vh, F);
+  Prim<R> s = ns_prim(c, Uh);
+  ns_visc(c, s, Vh, D, F);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) E[SM::FH + (f * 5 + v) * NF + q] = F[v];
+  for (int v = 0; v < 5; ++v) E[SM::FH + (f * 5 + v) * NF + q] = -F[v];
 }
 
-// interior fluxes and divergence along line q of flux-point family D
+// interior flux at flux point r (1 <= r <= N-1) of line q of family D
 template <int N, typename R, int D>
-__device__ __forceinline__ void ns_line_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q) {
+__device__ __forceinline__ void ns_iflux_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q, int r) {
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   int base, stride;
   line_of<3, N>(D, q, base, stride);
-  R ul[5][N], gl[15][N];
+  R w[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) {
+    R x = op.Lint[0][c];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) ul[v][c] = E[SM::U + v * NP + base + c * stride];
-#pragma unroll
-    for (int w = 0; w < 15; ++w) gl[w][c] = E[SM::G + w * NP + base + c * stride];
+    for (int k = 1; k < N - 1; ++k) x = (r == k + 1) ? op.Lint[k][c] : x;
+    w[c] = x;
   }
-  R Fl[N + 1][5];
+  R Uf[5], Gf[15];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    Fl[0][v] = E[SM::FH + ((2 * D) * 5 + v) * NF + q];
-    Fl[N][v] = E[SM::FH + ((2 * D + 1) * 5 + v) * NF + q];
+    const R *u = E + SM::U + v * NP + base;
+    R acc = R(0);
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc += w[c] * u[c * stride];
+    Uf[v] = acc;
   }
 #pragma unroll
-  for (int rr = 1; rr < N; ++rr) {
-    R Uf[5], Gf[15];
+  for (int m = 0; m < 15; ++m) {
+    const R *g = E + SM::G + m * NP + base;
+    R acc = R(0);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      R acc = R(0);
-#pragma unroll
-      for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * ul[v][c];
-      Uf[v] = acc;
-    }
-#pragma unroll
-    for (int w = 0; w < 15; ++w) {
-      R acc = R(0);
-#pragma unroll
-      for (int c = 0; c < N; ++c) acc += op.Lint[rr - 1][c] * gl[w][c];
-      Gf[w] = acc;
-    }
-    interior_flux<PHYS_NS, 5, R>(a, D, Uf, Gf, Fl[rr]);
+    for (int c = 0; c < N; ++c) acc += w[c] * g[c * stride];
+    Gf[m] = acc;
   }
+  R F[5];
+  interior_flux<PHYS_NS, 5, R>(a, D, Uf, Gf, F);
+  R *fo = E + SM::FI + ((D * (N - 1) + r - 1) * NF + q) * 5;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) fo[v] = F[v];
+}
+
+// divergence of variable v along line q of family D: -2/h_D M F over the
+// two interface fluxes and the N-1 interior ones, stored over the gradient
+template <int N, typename R, int D>
+__device__ __forceinline__ void ns_div_item(const KArgs &a, const NsOps<N, R> &op, R *E, int q, int v) {
+  using SM = NsSmem<N>;
+  constexpr int NP = SM::NP, NF = SM::NF;
+  int base, stride;
+  line_of<3, N>(D, q, base, stride);
+  R F[N + 1];
+  F[0] = E[SM::FH + ((2 * D) * 5 + v) * NF + q];
+  F[N] = E[SM::FH + ((2 * D + 1) * 5 + v) * NF + q];
+#pragma unroll
+  for (int c = 1; c < N; ++c) F[c] = E[SM::FI + ((D * (N - 1) + c - 1) * NF + q) * 5 + v];
   const R thd = (R)a.two_over_h[D];
 #pragma unroll
-  for (int ai = 0; ai < N; ++ai)
+  for (int ai = 0; ai < N; ++ai) {
+    R acc = R(0);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      R acc = R(0);
-#pragma unroll
-      for (int c = 0; c <= N; ++c) acc += op.M[ai][c] * Fl[c][v];
-      E[SM::RS + (D * 5 + v) * NP + base + ai * stride] = -thd * acc;
-    }
+    for (int c = 0; c <= N; ++c) acc += op.M[ai][c] * F[c];
+    E[SM::G + (D * 5 + v) * NP + base + ai * stride] = -thd * acc;
+  }
 }
 
 // What the right-hand-side kernel does with R at the solution points:
@@ -314,7 +350,7 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
 }
 
 template <int N, typename R, bool COMPACT>
-__global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
+__global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
                                                 double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep) {
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
@@ -331,19 +367,25 @@ __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, co
   for (int t = tid; t < nb * 18; t += nth) {
     int el = t / 18, k = t % 18;
     int e = e0 + el;
-    int nx = a.nel[0], ny = a.nel[1], nz = a.nel[2];
-    int c[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
-    const int ext[3] = {nx, ny, nz};
-    auto step = [&](int d, int s) { c[d] = s ? (c[d] + 1 == ext[d] ? 0 : c[d] + 1) : (c[d] == 0 ? ext[d] - 1 : c[d] - 1); };
+    const int nx = a.nel[0], ny = a.nel[1], nz = a.nel[2];
+    int cx = e % nx, cy = (e / nx) % ny, cz = e / (nx * ny);
+    // the one or two steps of neighbour k: (direction, side) pairs
+    int d0, s0, d1 = -1, s1 = 0;
     if (k < 6) {
-      step(k >> 1, k & 1);
+      d0 = k >> 1;
+      s0 = k & 1;
     } else {
       int ed = k - 6, P = ed >> 2;
-      int lo = P == 2 ? 1 : 0, hi = P == 0 ? 1 : 2;
-      step(lo, (ed >> 1) & 1);
-      step(hi, ed & 1);
+      d0 = P == 2 ? 1 : 0;
+      s0 = (ed >> 1) & 1;
+      d1 = P == 0 ? 1 : 2;
+      s1 = ed & 1;
     }
-    snb[el][k] = c[0] + nx * (c[1] + ny * c[2]);
+    auto wrap = [](int c, int s, int ext) { return s ? (c + 1 == ext ? 0 : c + 1) : (c == 0 ? ext - 1 : c - 1); };
+    if (d0 == 0 || d1 == 0) cx = wrap(cx, d0 == 0 ? s0 : s1, nx);
+    if (d0 == 1 || d1 == 1) cy = wrap(cy, d0 == 1 ? s0 : s1, ny);
+    if (d0 == 2 || d1 == 2) cz = wrap(cz, d0 == 2 ? s0 : s1, nz);
+    snb[el][k] = cx + nx * (cy + ny * cz);
   }
   {
     constexpr int W = (NP % 2 == 0) ? 2 : 1;
@@ -418,37 +460,57 @@ __global__ void __launch_bounds__(256) k_rhs_ns(const double *__restrict__ U, co
     }
   }
   __syncthreads();
-  // P3: interface fluxes, face-major work items
-  for (int t = tid; t < 6 * epb * NF; t += nth) {
-    int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
-    if (el >= nb) continue;
-    R *E = sm + el * SM::TOTAL;
-    switch (f) {
-      case 0: ns_face_item<N, R, COMPACT, 0, 0>(a, op, E, q); break;
-      case 1: ns_face_item<N, R, COMPACT, 0, 1>(a, op, E, q); break;
-      case 2: ns_face_item<N, R, COMPACT, 1, 0>(a, op, E, q); break;
-      case 3: ns_face_item<N, R, COMPACT, 1, 1>(a, op, E, q); break;
-      case 4: ns_face_item<N, R, COMPACT, 2, 0>(a, op, E, q); break;
-      default: ns_face_item<N, R, COMPACT, 2, 1>(a, op, E, q); break;
+  // P3: interface fluxes, face-major work items; the same thread takes the
+  // same face point in both passes, so the second reads its own LDS writes
+  auto p3 = [&](auto Pc) {
+    constexpr int PART = decltype(Pc)::value;
+    for (int t = tid; t < 6 * epb * NF; t += nth) {
+      int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+      if (el >= nb) continue;
+      R *E = sm + el * SM::TOTAL;
+      switch (f) {
+        case 0: ns_face_item<N, R, COMPACT, 0, 0, PART>(a, op, E, q); break;
+        case 1: ns_face_item<N, R, COMPACT, 0, 1, PART>(a, op, E, q); break;
+        case 2: ns_face_item<N, R, COMPACT, 1, 0, PART>(a, op, E, q); break;
+        case 3: ns_face_item<N, R, COMPACT, 1, 1, PART>(a, op, E, q); break;
+        case 4: ns_face_item<N, R, COMPACT, 2, 0, PART>(a, op, E, q); break;
+        default: ns_face_item<N, R, COMPACT, 2, 1, PART>(a, op, E, q); break;
+      }
     }
-  }
+  };
+  p3(std::integral_constant<int, 0>{});
+  p3(std::integral_constant<int, 1>{});
   __syncthreads();
-  // P4: interior fluxes and divergence, direction-major line items
-  for (int t = tid; t < 3 * epb * NF; t += nth) {
-    int d = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+  // P4: interior fluxes, items ordered (direction, flux point, element, line)
+  for (int t = tid; t < 3 * (N - 1) * epb * NF; t += nth) {
+    int d = t / ((N - 1) * epb * NF), r0 = t % ((N - 1) * epb * NF);
+    int r = 1 + r0 / (epb * NF), w = r0 % (epb * NF), el = w / NF, q = w % NF;
     if (el >= nb) continue;
     R *E = sm + el * SM::TOTAL;
     switch (d) {
-      case 0: ns_line_item<N, R, 0>(a, op, E, q); break;
-      case 1: ns_line_item<N, R, 1>(a, op, E, q); break;
-      default: ns_line_item<N, R, 2>(a, op, E, q); break;
+      case 0: ns_iflux_item<N, R, 0>(a, op, E, q, r); break;
+      case 1: ns_iflux_item<N, R, 1>(a, op, E, q, r); break;
+      default: ns_iflux_item<N, R, 2>(a, op, E, q, r); break;
     }
   }
   __syncthreads();
-  // P5: sum of the three directional contributions
+  // P5: divergence per line and variable, items ordered (direction, element,
+  // variable, line); then the three contributions summed in FP64
+  for (int t = tid; t < 3 * epb * 5 * NF; t += nth) {
+    int d = t / (epb * 5 * NF), r0 = t % (epb * 5 * NF);
+    int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
+    if (el >= nb) continue;
+    R *E = sm + el * SM::TOTAL;
+    switch (d) {
+      case 0: ns_div_item<N, R, 0>(a, op, E, q, v); break;
+      case 1: ns_div_item<N, R, 1>(a, op, E, q, v); break;
+      default: ns_div_item<N, R, 2>(a, op, E, q, v); break;
+    }
+  }
+  __syncthreads();
   for (int t = tid; t < nb * 5 * NP; t += nth) {
     int el = t / (5 * NP), r = t % (5 * NP);
-    const R *E = sm + el * SM::TOTAL + SM::RS;
+    const R *E = sm + el * SM::TOTAL + SM::G;
     double Rv = (double)E[r] + (double)E[5 * NP + r] + (double)E[10 * NP + r];
     long long i = (long long)e0 * 5 * NP + t;
     if (ep.mode == 0) {
