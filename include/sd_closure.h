@@ -51,9 +51,12 @@ int sd_mlp_forward(const sd_mlp_shape *shape, const float *P, const uint16_t *Wb
 int sd_mlp_backward(const sd_mlp_shape *shape, const uint16_t *Wb, void *work, const float *dY, int batch,
                     float *grad, void *stream);
 
-/* Mean square error of Y against T (n values): dY = 2 (Y - T) / n and the
- * loss into *loss (device FP64 scalar); deterministic reduction. */
-int sd_mse(const float *Y, const float *T, long long n, float *dY, double *loss, void *stream);
+/* Weighted mean square error of Y against T, both [rows][cols]:
+ *     loss = sum_r w[r] sum_c (Y - T)^2 / (rows cols),  dY = 2 w[r] (Y - T) / (rows cols),
+ * with w [rows] per-row weights (NULL = all ones); the loss goes to *loss
+ * (device FP64 scalar), reduced in a fixed order. */
+int sd_mse(const float *Y, const float *T, const float *w, long long rows, int cols, float *dY, double *loss,
+           void *stream);
 
 /* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on P with moments
  * m, v (FP32, same length), then Wb = bf16(P). */
@@ -70,11 +73,12 @@ int sd_filter(const double *fine, const int *nel_fine, int ratio, int p, int nv,
 /* Closure of an SD context (3-D Navier-Stokes): every later right-hand side
  * (sd_rhs, and each stage of sd_rk_step) adds to element e
  *     C_e = out_scale[v] * net((u_e[v] - in_shift[v]) / in_scale[v])
- * unless C_e holds a non-finite value or max|C_e| > max|R_e| (then C_e = 0
- * for that element).  n_in = n_out = 5 (p+1)^3.  P and Wb stay owned by the
- * caller and are read at each evaluation.  P = NULL switches the closure off. */
+ * unless C_e holds a non-finite value or, with max_ratio > 0,
+ * max|C_e| > max_ratio * max|R_e| (then C_e = 0 for that element).
+ * n_in = n_out = 5 (p+1)^3.  P and Wb stay owned by the caller and are read
+ * at each evaluation.  P = NULL switches the closure off. */
 int sd_closure_set(sd_ctx *ctx, const sd_mlp_shape *shape, const float *P, const uint16_t *Wb,
-                   const float *in_shift, const float *in_scale, const float *out_scale);
+                   const float *in_shift, const float *in_scale, const float *out_scale, float max_ratio);
 
 /* Number of element corrections discarded since the last sd_closure_set
  * (waits for the context's stream). */

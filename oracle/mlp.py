@@ -91,10 +91,13 @@ def backward(cache, dy):
     return g
 
 
-def mse(y, t):
-    """Mean square error and its gradient with respect to y."""
+def mse(y, t, w=None):
+    """Mean square error of y against t ([rows, cols]), each row weighted by
+    w[row] (default 1), and its gradient with respect to y."""
     d = y - t
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    wr = np.ones(d.shape[0]) if w is None else np.asarray(w, dtype=np.float64)
+    wd = wr.reshape((-1,) + (1,) * (d.ndim - 1)) * d
+    return float(np.sum(wd * d) / d.size), 2.0 * wd / d.size
 
 
 def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -128,15 +128,17 @@ __global__ void k_colsum(const float *__restrict__ x, int B, int N, float *__res
 }
 
 // dY = 2 (Y - T) / n and per-block partial sums of (Y - T)^2
-__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ Y, const float *__restrict__ T, long long n,
+__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ Y, const float *__restrict__ T,
+                                             const float *__restrict__ w, long long n, int cols,
                                              float *__restrict__ dY, double *__restrict__ part) {
   __shared__ double red[256];
   double acc = 0.0;
   const float scale = 2.0f / (float)n;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     float d = Y[i] - T[i];
-    dY[i] = scale * d;
-    acc += (double)d * (double)d;
+    float wr = w ? w[i / cols] : 1.0f;
+    dY[i] = scale * wr * d;
+    acc += (double)wr * ((double)d * (double)d);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -224,6 +226,7 @@ __global__ void __launch_bounds__(256) k_filter(const double *__restrict__ fine,
 // Closure input: X[e][v n^3 + pt] = (u[e][v][pt] - shift[v]) / scale[v]
 struct ClosureNorm {
   float shift[5], scale[5], out_scale[5];
+  float max_ratio;        // <= 0: no magnitude bound
 };
 
 __global__ void k_closure_input(const double *__restrict__ u, float *__restrict__ X, long long n, int np,

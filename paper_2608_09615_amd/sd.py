@@ -95,12 +95,12 @@ def load_library(path=LIB_PATH):
     L.sd_mlp_round_weights.argtypes = [sp, vp, vp, vp]
     L.sd_mlp_forward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.sd_mlp_backward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp]
-    L.sd_mse.argtypes = [vp, vp, ctypes.c_longlong, vp, vp, vp]
+    L.sd_mse.argtypes = [vp, vp, vp, ctypes.c_longlong, ctypes.c_int, vp, vp, vp]
     L.sd_mlp_adam.argtypes = [sp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, vp]
     L.sd_filter.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     L.sd_closure_set.argtypes = [vp, sp, vp, vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
-                                 ctypes.POINTER(ctypes.c_float)]
+                                 ctypes.POINTER(ctypes.c_float), ctypes.c_float]
     L.sd_closure_rejected.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
@@ -209,17 +209,19 @@ class SD:
         _check(load_library().sd_timing_read(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
 
-    def closure_set(self, mlp, in_shift, in_scale, out_scale):
+    def closure_set(self, mlp, in_shift=None, in_scale=None, out_scale=None, max_ratio=1.0):
         """Add the network ``mlp`` (an :class:`Mlp`) as a per-element closure;
-        ``mlp=None`` switches it off."""
+        ``mlp=None`` switches it off.  An element's correction is discarded
+        when non-finite or, with ``max_ratio`` > 0, larger in max norm than
+        ``max_ratio`` times its right-hand side."""
         f5 = ctypes.c_float * 5
         if mlp is None:
-            _check(load_library().sd_closure_set(self._ctx, None, None, None, None, None, None))
+            _check(load_library().sd_closure_set(self._ctx, None, None, None, None, None, None, 0.0))
             self._closure = None
             return
         self._closure = mlp
         _check(load_library().sd_closure_set(self._ctx, ctypes.byref(mlp.shape), _ptr(mlp.P), _ptr(mlp.Wb),
-                                             f5(*in_shift), f5(*in_scale), f5(*out_scale)))
+                                             f5(*in_shift), f5(*in_scale), f5(*out_scale), float(max_ratio)))
 
     def closure_rejected(self):
         n = ctypes.c_longlong()
@@ -302,9 +304,15 @@ class Mlp:
                                           _stream()))
 
 
-def mse(Y, T, dY, loss):
-    """dY = 2 (Y - T) / n and loss (one-element FP64 device tensor)."""
-    _check(load_library().sd_mse(_ptr(Y), _ptr(T), Y.numel(), _ptr(dY), _ptr(loss), _stream()))
+def mse(Y, T, dY, loss, w=None):
+    """Row-weighted MSE of Y [rows, cols] against T: dY = 2 w (Y - T) / n and
+    the loss into a one-element FP64 device tensor; ``w`` [rows] FP32 or None."""
+    if Y.dim() != 2:
+        raise ValueError("Y must be [rows, cols]")
+    if w is not None and w.numel() != Y.shape[0]:
+        raise ValueError("w must hold one weight per row")
+    _check(load_library().sd_mse(_ptr(Y), _ptr(T), None if w is None else _ptr(w), Y.shape[0], Y.shape[1],
+                                 _ptr(dY), _ptr(loss), _stream()))
 
 
 def filter_state(fine, nel_fine, ratio, p, nv):

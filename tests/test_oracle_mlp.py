@@ -107,3 +107,24 @@ def test_filter_preserves_integrals():
     If = np.einsum("evkji,kji->v", Uf, w3) / r ** 3
     Ic = np.einsum("evkji,kji->v", Uc, w3)
     assert np.abs(If - Ic).max() < 1e-12 * np.abs(Uf).sum()
+
+
+def test_weighted_mse_definition_and_gradient():
+    """Row weights: w = 1 is the plain mean, integer weights equal repeating
+    rows (with the count of values rescaled), and the gradient matches
+    central differences."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    y, t = rng.normal(size=(5, 7)), rng.normal(size=(5, 7))
+    l1, g1 = M.mse(y, t, np.ones(5))
+    assert l1 == pytest.approx(float(np.mean((y - t) ** 2)), rel=1e-14)
+    w = np.array([1, 2, 0, 3, 1])
+    lw, gw = M.mse(y, t, w)
+    rep = np.repeat(np.arange(5), w)
+    assert lw * 5 == pytest.approx(M.mse(y[rep], t[rep])[0] * len(rep), rel=1e-13)
+    h = 1e-6
+    for (i, j) in ((0, 0), (3, 4), (2, 6)):
+        yp, ym = y.copy(), y.copy()
+        yp[i, j] += h
+        ym[i, j] -= h
+        fd = (M.mse(yp, t, w)[0] - M.mse(ym, t, w)[0]) / (2 * h)
+        assert gw[i, j] == pytest.approx(fd, rel=1e-7, abs=1e-12)
