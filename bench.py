@@ -46,12 +46,13 @@ def parse():
     ap.add_argument("--nel", type=int, default=32)
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--scheme", default="compact")
+    ap.add_argument("--Re", type=float, default=1600.0)
     ap.add_argument("--ke-steps", type=int, default=150, help="RK4 steps of the FP32-vs-FP64 KE check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (calibrates byte counters)")
-    ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--precisions", default="fp32,fp64", help="fp32 and fp64 always for the JSON line; bf16x3 optional")
     return ap.parse_args()
 
 
@@ -60,7 +61,7 @@ def run_path(torch, W, args, precision, U0, dt):
     lo, hi = W.tgv_domain()
     nel = (args.nel,) * 3
     sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi,
-            Re=1600.0, Ma=0.1, Pr=0.71, gamma=1.4)
+            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4)
     u = torch.from_numpy(U0).to("cuda")
     for _ in range(args.warmup):
         sd.rk_step(u, dt)
@@ -98,7 +99,7 @@ def ke_error(torch, W, args, U0, dt, nsteps):
     nel = (args.nel,) * 3
     hist = {}
     for precision in ("fp64", "fp32"):
-        sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi)
+        sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi, Re=args.Re)
         u = torch.from_numpy(U0).to("cuda")
         h = [sd.diagnostics(u)["ke"]]
         for s in range(nsteps):
@@ -120,7 +121,7 @@ def cpu_baseline(W, args, U0):
     threads = min(os.cpu_count() or 1, 16)
     n = min(args.cpu_sample, ne)
     sel = np.arange(n, dtype=np.int64)
-    prm = O.make_params("ns", Re=1600.0, Ma=0.1, Pr=0.71)
+    prm = O.make_params("ns", Re=args.Re, Ma=0.1, Pr=0.71)
     t0 = time.perf_counter()
     O.rhs_3d_elems(U0, nel, lo, hi, args.p, args.scheme, prm, sel, nthreads=threads)
     sec = time.perf_counter() - t0
@@ -161,6 +162,9 @@ def main():
     r64 = run_path(torch, W, args, "fp64", U0, dt) if "fp64" in precs else None
     if r64:
         print(f"bench: fp64 {r64['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    rbf = run_path(torch, W, args, "bf16x3", U0, dt) if "bf16x3" in precs else None
+    if rbf:
+        print(f"bench: bf16x3 {rbf['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
     if r32 is None or r64 is None:
         return
     kerr, tke = ke_error(torch, W, args, U0, dt, args.ke_steps) if args.ke_steps > 0 else (None, 0.0)
@@ -195,13 +199,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"TGV Re=1600 Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}",
+        "config": {"workload": f"TGV Re={args.Re:g} Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}",
                    "dof": dof, "step": "one RK4 step = 4 RHS + 4 FP64 stage updates",
                    "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
         "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs"),
         "fp64": {"value": r64["gdofs"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
                  "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_traces+k_rhs")},
     }
+    if rbf:
+        rec["bf16x3"] = {"value": rbf["gdofs"], "ms_per_step": rbf["ms_per_step"], "dtype": "f32+bf16x3",
+                         "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs")}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0)
     print(json.dumps(rec), flush=True)

@@ -28,6 +28,7 @@
 // wavefronts share a compute unit.
 #pragma once
 
+#include <cstring>
 #include <type_traits>
 
 #include "sd_internal.h"
@@ -57,6 +58,72 @@ struct NsOps {
 };
 
 __host__ __device__ constexpr int pad4(int x) { return (x + 3) / 4 * 4; }
+
+// BF16x3 split precision (precision SD_BF16X3): the gradient and divergence
+// line contractions run on the 16-block 4x4x4 BF16 matrix-core instruction.
+// Each lane owns one column (a line of one variable): its K inputs go in the
+// B operand, lane l % 4 of every block supplies row l % 4 of the operator in
+// the A operand, and the lane receives its column's four outputs.  Operator
+// and data are split into hi + lo BF16 parts; hi*hi + hi*lo + lo*hi is
+// accumulated in FP32 (the lo*lo term, ~2^-18 relative, is dropped).  Both
+// operators annihilate constants (with the neighbour-trace term of the
+// gradient), so each column is shifted by its first value before the split:
+// exact algebra that leaves the split error proportional to the variation
+// along the line rather than to its level.  Operators are padded to
+// multiples of 4 in rows and in K.
+template <int N>
+struct alignas(16) NsSplitOps {
+  static constexpr int RC = (N + 3) / 4;       // 4-row chunks of the outputs
+  static constexpr int KA = (N + 3) / 4;       // K chunks of the gradient operator (K = N)
+  static constexpr int KM = (N + 4) / 4;       // K chunks of the divergence operator (K = N + 1)
+  uint16_t Ahi[4 * RC][4 * KA], Alo[4 * RC][4 * KA];
+  uint16_t Mhi[4 * RC][4 * KM], Mlo[4 * RC][4 * KM];
+};
+
+typedef short mf_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo + O(2^-18 |x|), both BF16 rounded to nearest even (finite x)
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
+}
+__device__ __forceinline__ void split_bf16(float x, short &h, short &l) {
+  const uint32_t hb = bf16_rne_bits(x);
+  h = (short)(hb >> 16);
+  l = (short)(bf16_rne_bits(x - __uint_as_float(hb)) >> 16);
+}
+
+// y[0 .. 4 RC) = Op x for this lane's column x[0 .. K); Ohi/Olo rows in LDS
+template <int K, int RC, int KC, int W>
+__device__ __forceinline__ void split_matvec(const uint16_t (*Ohi)[W], const uint16_t (*Olo)[W], const float *x,
+                                             float *y, int lane) {
+  mf_bf16x4 xh[KC], xl[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      short h, l;
+      split_bf16(4 * kc + k < K ? x[4 * kc + k] : 0.0f, h, l);
+      xh[kc][k] = h;
+      xl[kc][k] = l;
+    }
+  const int i = lane & 3;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) {
+    mf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const mf_bf16x4 ah = *reinterpret_cast<const mf_bf16x4 *>(&Ohi[4 * r + i][4 * kc]);
+      const mf_bf16x4 al = *reinterpret_cast<const mf_bf16x4 *>(&Olo[4 * r + i][4 * kc]);
+      acc = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ah, xh[kc], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ah, xl[kc], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(al, xh[kc], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[4 * r + j] = acc[j];
+  }
+}
 
 template <int N>
 struct NsSmem {
@@ -349,16 +416,24 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
   }
 }
 
-template <int N, typename R, bool COMPACT>
+template <int N, typename R, bool COMPACT, bool SPLIT = false>
 __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
-                                                double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep) {
+                                                double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep,
+                                                NsSplitOps<N> spo) {
+  static_assert(!SPLIT || sizeof(R) == 4, "BF16x3 works on the FP32 kernel");
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   constexpr int XS = trace_stride(3, N, 5), FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
   extern __shared__ double2 smem_ns[];          // 16-byte aligned dynamic LDS
   R *sm = reinterpret_cast<R *>(smem_ns);
   __shared__ int snb[kNsMaxEpb][18];
+  __shared__ NsSplitOps<SPLIT ? N : 1> ssp;
   const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (SPLIT) {
+    constexpr int WORDS = sizeof(NsSplitOps<N>) / 4;
+    for (int t = tid; t < WORDS; t += nth)
+      reinterpret_cast<uint32_t *>(&ssp)[t] = reinterpret_cast<const uint32_t *>(&spo)[t];
+  }
   const int epb = a.epb;
   const int e0 = blockIdx.x * epb;
   const int nb = min(epb, (int)(a.ne - e0));
@@ -430,6 +505,46 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
   }
   __syncthreads();
   // P2: gradient at the solution points
+  if constexpr (SPLIT) {
+    // one column per (direction, element, variable, line):
+    // g = (2/h_m) [A x + (Mc0 tn0 + Mc1 tn1) / 2],  A = D - (Mc0 Lend0^T + Mc1 Lend1^T) / 2
+    using SO = NsSplitOps<N>;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+    const int ncol = 3 * epb * 5 * NF;
+    for (int b0 = wave * 64; b0 < ncol; b0 += nwaves * 64) {
+      const int col = b0 + lane;
+      const int m = col / (epb * 5 * NF), r0 = col % (epb * 5 * NF);
+      const int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
+      const bool ok = col < ncol && el < nb;
+      R x[N];
+      R tn0 = R(0), tn1 = R(0);
+      int base = 0, stride = 0;
+      R *E = sm + (ok ? el : 0) * SM::TOTAL;
+#pragma unroll
+      for (int c = 0; c < N; ++c) x[c] = R(0);
+      if (ok) {
+        line_of<3, N>(m, q, base, stride);
+#pragma unroll
+        for (int c = 0; c < N; ++c) x[c] = E[SM::U + v * NP + base + c * stride];
+        tn0 = E[SM::TNN + ((2 * m) * 10 + v) * NF + q];
+        tn1 = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + q];
+        const R x0 = x[0];
+#pragma unroll
+        for (int c = 0; c < N; ++c) x[c] -= x0;
+        tn0 -= x0;
+        tn1 -= x0;
+      }
+      float y[4 * SO::RC];
+      split_matvec<N, SO::RC, SO::KA>(ssp.Ahi, ssp.Alo, x, y, lane);
+      if (ok) {
+        const R th = (R)pick(m, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
+#pragma unroll
+        for (int ai = 0; ai < N; ++ai)
+          E[SM::G + (m * 5 + v) * NP + base + ai * stride] =
+              th * (y[ai] + R(0.5) * (op.Mc[0][ai] * tn0 + op.Mc[1][ai] * tn1));
+      }
+    }
+  } else
   for (int t = tid; t < nb * NP; t += nth) {
     int el = t / NP, pt = t % NP;
     R *E = sm + el * SM::TOTAL;
@@ -496,6 +611,39 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
   __syncthreads();
   // P5: divergence per line and variable, items ordered (direction, element,
   // variable, line); then the three contributions summed in FP64
+  if constexpr (SPLIT) {
+    using SO = NsSplitOps<N>;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+    const int ncol = 3 * epb * 5 * NF;
+    for (int b0 = wave * 64; b0 < ncol; b0 += nwaves * 64) {
+      const int col = b0 + lane;
+      const int d = col / (epb * 5 * NF), r0 = col % (epb * 5 * NF);
+      const int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
+      const bool ok = col < ncol && el < nb;
+      R F[N + 1];
+      int base = 0, stride = 0;
+      R *E = sm + (ok ? el : 0) * SM::TOTAL;
+#pragma unroll
+      for (int c = 0; c <= N; ++c) F[c] = R(0);
+      if (ok) {
+        line_of<3, N>(d, q, base, stride);
+        F[0] = E[SM::FH + ((2 * d) * 5 + v) * NF + q];
+        F[N] = E[SM::FH + ((2 * d + 1) * 5 + v) * NF + q];
+#pragma unroll
+        for (int c = 1; c < N; ++c) F[c] = E[SM::FI + ((d * (N - 1) + c - 1) * NF + q) * 5 + v];
+        const R f0 = F[0];
+#pragma unroll
+        for (int c = 0; c <= N; ++c) F[c] -= f0;
+      }
+      float y[4 * SO::RC];
+      split_matvec<N + 1, SO::RC, SO::KM>(ssp.Mhi, ssp.Mlo, F, y, lane);
+      if (ok) {
+        const R thd = (R)pick(d, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
+#pragma unroll
+        for (int ai = 0; ai < N; ++ai) E[SM::G + (d * 5 + v) * NP + base + ai * stride] = -thd * y[ai];
+      }
+    }
+  } else
   for (int t = tid; t < 3 * epb * 5 * NF; t += nth) {
     int d = t / (epb * 5 * NF), r0 = t % (epb * 5 * NF);
     int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
@@ -525,6 +673,43 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
       }
     }
   }
+}
+
+// BF16 bits of a float, round to nearest even (host)
+inline uint16_t host_bf16(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+inline float host_from_bf16(uint16_t h) {
+  uint32_t b = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &b, 4);
+  return x;
+}
+
+// Split operators of the BF16x3 path from the operator table: the gradient
+// operator D - (Mc0 Lend0^T + Mc1 Lend1^T) / 2 (the correction of the
+// auxiliary gradient by the common solution, regrouped) and the divergence
+// operator M, each rounded to FP32 and split into hi + lo BF16.
+template <int N>
+NsSplitOps<N> make_split_ops(const double *t) {
+  const OpsLayout O = ops_layout(N);
+  NsSplitOps<N> s{};
+  auto put = [](uint16_t *hi, uint16_t *lo, double v) {
+    float f = (float)v;
+    *hi = host_bf16(f);
+    *lo = host_bf16(f - host_from_bf16(*hi));
+  };
+  for (int i = 0; i < N; ++i) {
+    for (int c = 0; c < N; ++c) {
+      double a = t[O.D + i * N + c] - 0.5 * (t[O.Mc + i] * t[O.Lend + c] + t[O.Mc + N + i] * t[O.Lend + N + c]);
+      put(&s.Ahi[i][c], &s.Alo[i][c], a);
+    }
+    for (int c = 0; c <= N; ++c) put(&s.Mhi[i][c], &s.Mlo[i][c], t[O.M + i * (N + 1) + c]);
+  }
+  return s;
 }
 
 template <int N, typename R>

@@ -18,6 +18,14 @@ FP64_TOL = 1e-12
 # bound is a few hundred FP32 ulps of the largest term, normwise.
 FP32_TOL_SCALAR = 2e-5
 FP32_TOL_NS = 2e-4
+# BF16x3 (gradient and divergence contractions as hi*hi + hi*lo + lo*hi BF16
+# products, FP32 accumulation; everything else as FP32): each split operand
+# carries ~2^-18 relative error, so one directional divergence is good to
+# ~1e-5 of its size.  The density and energy residuals are sums of three
+# directional divergences that cancel to ~1/300 of their size at Ma = 0.1
+# (div(rho u) and div((rho E + p) u) ~ Ma^2), which leaves ~3e-3 normwise in
+# those two variables (momentum ~3e-5); the gate is 1e-2.
+BF16X3_TOL_NS = 1e-2
 
 
 @pytest.fixture(scope="module")
@@ -108,6 +116,24 @@ def test_3d_ns_parity_fp32(torch_cuda, oracle_lib, scheme, p):
     assert err < FP32_TOL_NS
 
 
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 3, 4, 5])
+def test_3d_ns_parity_bf16x3(torch_cuda, oracle_lib, scheme, p):
+    """BF16x3 split-precision path (matrix-core gradient and divergence)
+    against the FP64 oracle; p = 4 and 5 take two row and K chunks."""
+    prm = oracle_lib.make_params("ns", Re=1600.0)
+    lo, hi = W.tgv_domain()
+    nel = (4, 3, 5)
+    U = W.perturbed_tgv_state(nel, p, seed=30 + p, noise=1e-3)
+    R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "bf16x3", lo, hi)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+    err = relerr(R, Ro)
+    per_var = [relerr(R.reshape(Ro.shape)[:, v:v + 1], Ro[:, v:v + 1]) for v in range(5)]
+    print(f"bf16x3 NS p={p} {scheme}: normwise relative error {err:.3e}, per variable "
+          + " ".join(f"{e:.2e}" for e in per_var))
+    assert err < BF16X3_TOL_NS
+
+
 @pytest.mark.parametrize("scheme,width", [("compact", 19), ("br1", 25)])
 def test_gpu_stencil_width(torch_cuda, oracle_lib, scheme, width):
     nel, p = (7, 7, 7), 2
@@ -182,7 +208,8 @@ def test_tgv_32cubed_sampled_parity(torch_cuda, oracle_lib):
     for scheme in ("compact", "br1"):
         Ro, sens = ulp_sensitivity(oracle_lib, U, nel, lo, hi, p, scheme, prm, sel)
         assert sens < 1e-11
-        for precision, tol in (("fp64", max(FP64_TOL, 4 * sens)), ("fp32", FP32_TOL_NS)):
+        for precision, tol in (("fp64", max(FP64_TOL, 4 * sens)), ("fp32", FP32_TOL_NS),
+                               ("bf16x3", BF16X3_TOL_NS)):
             R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", precision, lo, hi)
             err = relerr(R[sel], Ro)
             print(f"32^3 {scheme} {precision}: error {err:.3e} (ulp sensitivity {sens:.3e})")

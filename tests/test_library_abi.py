@@ -71,6 +71,7 @@ def _init(lib, dim=3, nel=(4, 4, 4), p=3, scheme=1, **kw):
     (dict(physics=9), -1),
     (dict(physics=1, pme_m=2.5), -1),
     (dict(precision=5), -1),
+    (dict(precision=2, physics=0), -5),          # BF16x3 is built for Navier-Stokes only
     (dict(Re=-1.0), -1),
 ])
 def test_invalid_arguments_are_rejected(lib, kw, code):
