@@ -56,6 +56,27 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(args, precision):
+    """HBM bytes per RK stage (k_traces_ns + k_rhs_ns) from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the workload differs or
+    a kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "rhs_traffic_tgv32p3.json")
+    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and os.path.exists(path)):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in sorted(glob.glob(os.path.join(ROOT, "paper_2608_09615_amd", "csrc", "*"))):
+        h.update(os.path.basename(src).encode())
+        with open(src, "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["per_stage_bytes"].get(precision)
+
+
 def run_path(torch, W, args, precision, U0, dt):
     from paper_2608_09615_amd import SD
     lo, hi = W.tgv_domain()
@@ -171,8 +192,9 @@ def main():
     dof = args.nel ** 3 * (args.p + 1) ** 3
     flop = FLOP_PER_DOF.get(args.p, 1430.0) * dof
 
-    def roof(r, peak_flops, name):
+    def roof(r, peak_flops, name, precision):
         t = r["rhs_ms_avg"] * 1e-3
+        traffic = measured_traffic(args, precision)
         alu = flop / t / 1e12
         hbm = BYTES_PER_DOF * dof / t / 1e9
         # binding ceiling: the lower of the ALU and HBM rooflines for this path
@@ -180,10 +202,10 @@ def main():
         ceil_hbm = PEAK_HBM_GBS * 1e9 / BYTES_PER_DOF
         if ceil_alu <= ceil_hbm:
             return {"bound": "alu", "achieved": alu, "peak": peak_flops, "unit": "TFLOP/s",
-                    "frac": alu / peak_flops, "traffic": None, "kernels": name,
+                    "frac": alu / peak_flops, "traffic": traffic, "traffic_unit": "B per RK stage", "kernels": name,
                     "rhs_ms": r["rhs_ms_avg"], "hbm_gbs_algorithmic": hbm}
         return {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": hbm / PEAK_HBM_GBS, "traffic": None, "kernels": name,
+                "frac": hbm / PEAK_HBM_GBS, "traffic": traffic, "traffic_unit": "B per RK stage", "kernels": name,
                 "rhs_ms": r["rhs_ms_avg"], "tflops_algorithmic": alu}
 
     rec = {
@@ -202,13 +224,13 @@ def main():
         "config": {"workload": f"TGV Re={args.Re:g} Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}",
                    "dof": dof, "step": "one RK4 step = 4 RHS + 4 FP64 stage updates",
                    "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
-        "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs"),
+        "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "fp32"),
         "fp64": {"value": r64["gdofs"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
-                 "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_traces+k_rhs")},
+                 "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_traces+k_rhs", "fp64")},
     }
     if rbf:
         rec["bf16x3"] = {"value": rbf["gdofs"], "ms_per_step": rbf["ms_per_step"], "dtype": "f32+bf16x3",
-                         "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs")}
+                         "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "bf16x3")}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0)
     print(json.dumps(rec), flush=True)
