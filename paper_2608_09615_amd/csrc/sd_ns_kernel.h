@@ -321,45 +321,21 @@ struct RkEpi {
   double *out;
 };
 
-// Element-local trace kernel for the Navier-Stokes system: the full trace
-// record of every element (face traces T, normal-gradient traces NN, edge
-// traces) is assembled in LDS and stored with contiguous vector stores.
+// Trace records of a block's elements, assembled in LDS: element el's state
+// [5][NP] (reference removed) sits at sm + el * PER + UO and its record (face
+// traces T, normal-gradient traces NN, edge traces) goes to sm + el * PER + XO.
+// Ends with a barrier.
 template <int N, typename R>
-__global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U, R *__restrict__ X, KArgs a,
-                                                   NsOps<N, R> op) {
+__device__ __forceinline__ void ns_trace_record(R *sm, int PER, int UO, int XO, int epb, int nb,
+                                                const NsOps<N, R> &op, int tid, int nth) {
   constexpr int NP = N * N * N, NF = N * N;
-  constexpr int XS = trace_stride(3, N, 5), FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
-  constexpr int PER = pad4(5 * NP) + pad4(XS);
-  extern __shared__ double2 smem_tr[];
-  R *sm = reinterpret_cast<R *>(smem_tr);
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int epb = a.epb;
-  const int e0 = blockIdx.x * epb;
-  const int nb = min(epb, (int)(a.ne - e0));
-  {
-    constexpr int W = (NP % 2 == 0) ? 2 : 1;
-    using V = typename VecT<double, W>::T;
-    const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
-    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
-      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
-      double u0 = a.U0[r / NP];
-      R *dst = sm + el * PER + r;
-      if constexpr (W == 2) {
-        V x = src[t];
-        dst[0] = (R)(x.x - u0);
-        dst[1] = (R)(x.y - u0);
-      } else {
-        dst[0] = (R)(src[t] - u0);
-      }
-    }
-  }
-  __syncthreads();
+  constexpr int FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
   // face traces and normal-gradient traces, face-major work items
   for (int t = tid; t < 6 * epb * NF; t += nth) {
     int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
     if (el >= nb) continue;
-    const R *u = sm + el * PER;
-    R *x = sm + el * PER + pad4(5 * NP);
+    const R *u = sm + el * PER + UO;
+    R *x = sm + el * PER + XO;
     auto item = [&](auto Dc, auto Sc) {
       constexpr int D = decltype(Dc)::value, S = decltype(Sc)::value, ff = 2 * D + S;
       int base, stride;
@@ -397,7 +373,7 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
     int ed = r / (5 * N), w = r % (5 * N), v = w / N, at = w % N;
     int P = ed >> 2, slo = (ed >> 1) & 1, shi = ed & 1;
     int lo = P == 2 ? 1 : 0, hi = P == 0 ? 1 : 2, t3 = 3 - lo - hi;
-    R *x = sm + el * PER + pad4(5 * NP);
+    R *x = sm + el * PER + XO;
     const R *tf = x + (2 * lo + slo) * FS + v * NF;
     R acc = R(0);
 #pragma unroll
@@ -405,21 +381,77 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
     x[EO + (ed * 5 + v) * N + at] = acc;
   }
   __syncthreads();
-  {
-    constexpr int W = vec_width<R, XS>();
-    using V = typename VecT<R, W>::T;
-    V *dst = reinterpret_cast<V *>(X + (long long)e0 * XS);
-    for (int t = tid; t < nb * XS / W; t += nth) {
-      int el = (t * W) / XS, r = (t * W) % XS;
-      dst[t] = *reinterpret_cast<const V *>(sm + el * PER + pad4(5 * NP) + r);
-    }
+}
+
+// contiguous vector store of the block's trace records to X
+template <int N, typename R>
+__device__ __forceinline__ void ns_store_records(const R *sm, int PER, int XO, R *X, long long e0, int nb, int tid,
+                                                 int nth) {
+  constexpr int XS = trace_stride(3, N, 5);
+  constexpr int W = vec_width<R, XS>();
+  using V = typename VecT<R, W>::T;
+  V *dst = reinterpret_cast<V *>(X + e0 * XS);
+  for (int t = tid; t < nb * XS / W; t += nth) {
+    int el = (t * W) / XS, r = (t * W) % XS;
+    dst[t] = *reinterpret_cast<const V *>(sm + el * PER + XO + r);
   }
 }
+
+// Element-local trace kernel for the Navier-Stokes system: the full trace
+// record of every element is assembled in LDS and stored with contiguous
+// vector stores.
+template <int N, typename R>
+__global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U, R *__restrict__ X, KArgs a,
+                                                   NsOps<N, R> op) {
+  constexpr int NP = N * N * N;
+  constexpr int XS = trace_stride(3, N, 5);
+  constexpr int PER = pad4(5 * NP) + pad4(XS);
+  extern __shared__ double2 smem_tr[];
+  R *sm = reinterpret_cast<R *>(smem_tr);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int epb = a.epb;
+  const int e0 = blockIdx.x * epb;
+  const int nb = min(epb, (int)(a.ne - e0));
+  {
+    constexpr int W = (NP % 2 == 0) ? 2 : 1;
+    using V = typename VecT<double, W>::T;
+    const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
+    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
+      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
+      double u0 = a.U0[r / NP];
+      R *dst = sm + el * PER + r;
+      if constexpr (W == 2) {
+        V x = src[t];
+        dst[0] = (R)(x.x - u0);
+        dst[1] = (R)(x.y - u0);
+      } else {
+        dst[0] = (R)(src[t] - u0);
+      }
+    }
+  }
+  __syncthreads();
+  ns_trace_record<N, R>(sm, PER, 0, pad4(5 * NP), epb, nb, op, tid, nth);
+  ns_store_records<N, R>(sm, PER, pad4(5 * NP), X, e0, nb, tid, nth);
+}
+
+// Chained RK stages (fused path without a closure): the stage state between
+// stages is kept in compute precision with the reference state removed (the
+// value the kernel would round the FP64 state to), and each stage emits the
+// trace records of the next stage's state, so the trace kernel runs once per
+// step.  in_r: stage state to read instead of U (nullptr: U); out_r: where the
+// stage epilogue writes the next stage state (nullptr: FP64 epilogue of
+// RkEpi); xnext: trace records of out_r.
+template <typename R>
+struct NsChain {
+  const R *in_r;
+  R *out_r;
+  R *xnext;
+};
 
 template <int N, typename R, bool COMPACT, bool SPLIT = false>
 __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
                                                 double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep,
-                                                NsSplitOps<N> spo) {
+                                                NsSplitOps<N> spo, NsChain<R> ch) {
   static_assert(!SPLIT || sizeof(R) == 4, "BF16x3 works on the FP32 kernel");
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
@@ -462,7 +494,16 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     if (d0 == 2 || d1 == 2) cz = wrap(cz, d0 == 2 ? s0 : s1, nz);
     snb[el][k] = cx + nx * (cy + ny * cz);
   }
-  {
+  if (ch.in_r) {
+    // stage state already in compute precision, reference removed
+    constexpr int W = vec_width<R, 5 * NP>();
+    using V = typename VecT<R, W>::T;
+    const V *src = reinterpret_cast<const V *>(ch.in_r + (long long)e0 * 5 * NP);
+    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
+      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
+      *reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::U + r) = src[t];
+    }
+  } else {
     constexpr int W = (NP % 2 == 0) ? 2 : 1;
     using V = typename VecT<double, W>::T;
     const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
@@ -669,9 +710,23 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
         ep.out[i] = ep.u0[i] + ep.dt6 * accv;
       } else {
         ep.acc[i] = accv;
-        ep.out[i] = ep.u0[i] + ep.a * Rv;
+        const double w = ep.u0[i] + ep.a * Rv;
+        if (ch.out_r) {
+          // next stage state, as the next kernel would round it; the state
+          // region of LDS is dead here and takes it for the trace records
+          const R wr = (R)(w - a.U0[r / NP]);
+          ch.out_r[i] = wr;
+          sm[el * SM::TOTAL + SM::U + r] = wr;
+        } else {
+          ep.out[i] = w;
+        }
       }
     }
+  }
+  if (ch.out_r) {
+    __syncthreads();
+    ns_trace_record<N, R>(sm, SM::TOTAL, SM::U, SM::TNN, epb, nb, op, tid, nth);
+    ns_store_records<N, R>(sm, SM::TOTAL, SM::TNN, ch.xnext, e0, nb, tid, nth);
   }
 }
 
