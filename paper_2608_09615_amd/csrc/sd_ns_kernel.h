@@ -46,6 +46,13 @@ __host__ __device__ constexpr int ns_max_threads() {
   return (sizeof(R) == 8 && N >= 5) ? 256 : 512;
 }
 
+#ifndef SD_NS_SMEM_TARGET
+#define SD_NS_SMEM_TARGET (64 * 1024)
+#endif
+#ifndef SD_NS_THREADS_PER_ELEM
+#define SD_NS_THREADS_PER_ELEM 0
+#endif
+
 template <int N, typename R>
 struct NsOps {
   R Lend[2][N];
@@ -139,6 +146,31 @@ struct NsSmem {
   static constexpr int FI = (TNN + FIN <= FH) ? TNN : END;
   static constexpr int TOTAL = (FI == TNN) ? END : pad4(END + FIN);
 };
+
+// Launch shape of k_rhs_ns, fixed per instantiation so that the work-item
+// index arithmetic divides by compile-time constants: as many elements per
+// block as fit the LDS target (at most one full block of solution points and
+// kNsMaxEpb), and 4 n^2 threads per element (256 for four p = 3 elements):
+// with the face pass at ~137 VGPRs (three wavefronts per SIMD) this fills the
+// compute unit as far as the LDS of three such blocks allows.
+template <int N, typename R>
+__host__ __device__ constexpr int ns_epb() {
+#ifdef SD_NS_EPB
+  if (SD_NS_EPB > 0) return SD_NS_EPB;
+#endif
+  constexpr long long per = (long long)NsSmem<N>::TOTAL * (long long)sizeof(R);
+  long long e = (long long)(SD_NS_SMEM_TARGET) / per;
+  const long long cap = (256 / (N * N * N)) > 1 ? (256 / (N * N * N)) : 1;
+  if (e > cap) e = cap;
+  if (e > kNsMaxEpb) e = kNsMaxEpb;
+  return e < 1 ? 1 : (int)e;
+}
+template <int N, typename R>
+__host__ __device__ constexpr int ns_threads() {
+  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : 4 * N * N;
+  const int t = (ns_epb<N, R>() * tpe + 63) / 64 * 64;
+  return t < ns_max_threads<N, R>() ? t : ns_max_threads<N, R>();
+}
 
 // number of values moved per vector load for a contiguous run of CNT values
 template <typename R, int CNT>
@@ -460,13 +492,14 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
   R *sm = reinterpret_cast<R *>(smem_ns);
   __shared__ int snb[kNsMaxEpb][18];
   __shared__ NsSplitOps<SPLIT ? N : 1> ssp;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  constexpr int nth = ns_threads<N, R>();          // == blockDim.x
+  const int tid = threadIdx.x;
   if constexpr (SPLIT) {
     constexpr int WORDS = sizeof(NsSplitOps<N>) / 4;
     for (int t = tid; t < WORDS; t += nth)
       reinterpret_cast<uint32_t *>(&ssp)[t] = reinterpret_cast<const uint32_t *>(&spo)[t];
   }
-  const int epb = a.epb;
+  constexpr int epb = ns_epb<N, R>();              // == a.epb
   const int e0 = blockIdx.x * epb;
   const int nb = min(epb, (int)(a.ne - e0));
 
