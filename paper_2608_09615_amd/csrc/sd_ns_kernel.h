@@ -62,6 +62,11 @@ struct NsOps {
   R Mc[2][N];
   R rrow[2][N];
   R kap[2];
+  // auxiliary gradient along a line regrouped by linearity:
+  // D u + Mc0 (uh0 - Lend0 u) + Mc1 (uh1 - Lend1 u) with uh = (t + Lend u)/2
+  // = A u + hMc0 t0 + hMc1 t1, A = D - (Mc0 Lend0^T + Mc1 Lend1^T)/2
+  R A[N][N];
+  R hMc[2][N];
 };
 
 __host__ __device__ constexpr int pad4(int x) { return (x + 3) / 4 * 4; }
@@ -256,18 +261,14 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
 #pragma unroll
       for (int c = 0; c < N; ++c) vown += op.Lend[S][c] * g[c * stride];
       const R *tn = E + SM::TNN + (f * 10 + v) * NF + qs;
-      R dT = R(0), eL = R(0), eR = R(0);
+      // neighbour's gradient along m at this point, from its face trace
+      // along the line and the edge traces of its neighbours (regrouped A)
+      R acc = R(0);
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        R tv = tn[c * qstep];
-        dT += op.D[am][c] * tv;
-        eL += op.Lend[0][c] * tv;
-        eR += op.Lend[1][c] * tv;
-      }
+      for (int c = 0; c < N; ++c) acc += op.A[am][c] * tn[c * qstep];
       R eLn = E[SM::E + (e0i * 5 + v) * N + at];
       R eRn = E[SM::E + (e1i * 5 + v) * N + at];
-      R ehL = R(0.5) * (eLn + eL), ehR = R(0.5) * (eR + eRn);
-      R voth = thm * (dT + op.Mc[0][am] * (ehL - eL) + op.Mc[1][am] * (ehR - eR));
+      R voth = thm * (acc + op.hMc[0][am] * eLn + op.hMc[1][am] * eRn);
       Vh[m * 5 + v] = S == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
     }
   }
@@ -631,19 +632,12 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const R *u = E + SM::U + v * NP + base;
-        R acc = R(0), to0 = R(0), to1 = R(0);
+        R acc = R(0);
 #pragma unroll
-        for (int c = 0; c < N; ++c) {
-          R uv = u[c * stride];
-          acc += op.D[am][c] * uv;
-          to0 += op.Lend[0][c] * uv;      // own traces at the two m-faces
-          to1 += op.Lend[1][c] * uv;
-        }
+        for (int c = 0; c < N; ++c) acc += op.A[am][c] * u[c * stride];
         R tn0 = E[SM::TNN + ((2 * m) * 10 + v) * NF + qm];
         R tn1 = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + qm];
-        R uh0 = R(0.5) * (tn0 + to0), uh1 = R(0.5) * (to1 + tn1);
-        acc += op.Mc[0][am] * (uh0 - to0);
-        acc += op.Mc[1][am] * (uh1 - to1);
+        acc += op.hMc[0][am] * tn0 + op.hMc[1][am] * tn1;
         E[SM::G + (m * 5 + v) * NP + pt] = th * acc;
       }
     }
@@ -818,6 +812,12 @@ NsOps<N, R> make_ns_ops(const double *t) {
     for (int j = 0; j <= N; ++j) op.M[i][j] = (R)t[O.M + i * (N + 1) + j];
   op.kap[0] = (R)t[O.kap];
   op.kap[1] = (R)t[O.kap + 1];
+  for (int i = 0; i < N; ++i) {
+    for (int c = 0; c < N; ++c)
+      op.A[i][c] = (R)(t[O.D + i * N + c] - 0.5 * (t[O.Mc + i] * t[O.Lend + c] + t[O.Mc + N + i] * t[O.Lend + N + c]));
+    op.hMc[0][i] = (R)(0.5 * t[O.Mc + i]);
+    op.hMc[1][i] = (R)(0.5 * t[O.Mc + N + i]);
+  }
   return op;
 }
 
