@@ -137,12 +137,27 @@ __device__ __forceinline__ void split_matvec(const uint16_t (*Ohi)[W], const uin
   }
 }
 
+// Point values of an element in LDS: x-lines of N values at pitch PT
+// (PT = N + 1 in k_rhs_ns, so that the lines read by one wavefront spread
+// over the LDS banks; PT = N in k_traces_ns).  Point (i, j, k) sits at
+// i + PT (j + N k); line q of direction d as in the face-point numbering
+// (d = 0: q = j + N k; d = 1: q = i + N k; d = 2: q = i + N j).
+template <int N, int PT>
+__device__ __forceinline__ void ns_line(int d, int q, int &base, int &stride) {
+  if (d == 0) { base = q * PT; stride = 1; }
+  else if (d == 1) { base = (q % N) + PT * N * (q / N); stride = PT; }
+  else { base = (q % N) + PT * (q / N); stride = PT * N; }
+}
+template <int N, int PT>
+__device__ __forceinline__ int ns_pidx(int pt) { return (pt % N) + PT * (pt / N); }
+
 template <int N>
 struct NsSmem {
   static constexpr int NP = N * N * N, NF = N * N;
-  static constexpr int U = 0;                        // [5][NP]
-  static constexpr int G = pad4(U + 5 * NP);         // [3][5][NP]; P5: directional residuals
-  static constexpr int TNN = pad4(G + 15 * NP);      // [6][10][NF] neighbour T (v < 5) and NN (v >= 5)
+  static constexpr int PT = N + 1, NPP = N * N * PT;   // padded point count per variable
+  static constexpr int U = 0;                        // [5][NPP]
+  static constexpr int G = pad4(U + 5 * NPP);        // [3][5][NPP]; P5: directional residuals
+  static constexpr int TNN = pad4(G + 15 * NPP);     // [6][10][NF] neighbour T (v < 5) and NN (v >= 5)
   static constexpr int E = pad4(TNN + 60 * NF);      // [12][5][N] edge-neighbour edge traces
   static constexpr int FH = pad4(E + 60 * N);        // [6][5][NF] interface fluxes
   static constexpr int END = pad4(FH + 30 * NF);
@@ -202,11 +217,11 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
   R UL[5], UR[5], Uh[5], Vh[15], NNo[5];
   const R thd = (R)a.two_over_h[D];
   int base, stride;
-  line_of<3, N>(D, q, base, stride);
+  ns_line<N, SM::PT>(D, q, base, stride);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     // own face trace (and, compact, own normal-gradient trace) from the state
-    const R *u = E + SM::U + v * NP + base;
+    const R *u = E + SM::U + v * SM::NPP + base;
     R own = R(0), nn = R(0);
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -235,7 +250,7 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
     if constexpr (COMPACT) {
       vown = thd * (NNo[v] + op.kap[S] * Uh[v]);
     } else {
-      const R *g = E + SM::G + (D * 5 + v) * NP + base;
+      const R *g = E + SM::G + (D * 5 + v) * SM::NPP + base;
       R acc = R(0);
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += op.Lend[S][c] * g[c * stride];
@@ -256,7 +271,7 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
     const int e0i = edge_id(D, S, m, 0), e1i = edge_id(D, S, m, 1);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const R *g = E + SM::G + (m * 5 + v) * NP + base;
+      const R *g = E + SM::G + (m * 5 + v) * SM::NPP + base;
       R vown = R(0);
 #pragma unroll
       for (int c = 0; c < N; ++c) vown += op.Lend[S][c] * g[c * stride];
@@ -284,7 +299,7 @@ __device__ __forceinline__ void ns_iflux_item(const KArgs &a, const NsOps<N, R> 
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   int base, stride;
-  line_of<3, N>(D, q, base, stride);
+  ns_line<N, SM::PT>(D, q, base, stride);
   R w[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) {
@@ -296,7 +311,7 @@ __device__ __forceinline__ void ns_iflux_item(const KArgs &a, const NsOps<N, R> 
   R Uf[5], Gf[15];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const R *u = E + SM::U + v * NP + base;
+    const R *u = E + SM::U + v * SM::NPP + base;
     R acc = R(0);
 #pragma unroll
     for (int c = 0; c < N; ++c) acc += w[c] * u[c * stride];
@@ -304,7 +319,7 @@ __device__ __forceinline__ void ns_iflux_item(const KArgs &a, const NsOps<N, R> 
   }
 #pragma unroll
   for (int m = 0; m < 15; ++m) {
-    const R *g = E + SM::G + m * NP + base;
+    const R *g = E + SM::G + m * SM::NPP + base;
     R acc = R(0);
 #pragma unroll
     for (int c = 0; c < N; ++c) acc += w[c] * g[c * stride];
@@ -324,7 +339,7 @@ __device__ __forceinline__ void ns_div_item(const KArgs &a, const NsOps<N, R> &o
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   int base, stride;
-  line_of<3, N>(D, q, base, stride);
+  ns_line<N, SM::PT>(D, q, base, stride);
   R F[N + 1];
   F[0] = E[SM::FH + ((2 * D) * 5 + v) * NF + q];
   F[N] = E[SM::FH + ((2 * D + 1) * 5 + v) * NF + q];
@@ -336,7 +351,7 @@ __device__ __forceinline__ void ns_div_item(const KArgs &a, const NsOps<N, R> &o
     R acc = R(0);
 #pragma unroll
     for (int c = 0; c <= N; ++c) acc += op.M[ai][c] * F[c];
-    E[SM::G + (D * 5 + v) * NP + base + ai * stride] = -thd * acc;
+    E[SM::G + (D * 5 + v) * SM::NPP + base + ai * stride] = -thd * acc;
   }
 }
 
@@ -358,10 +373,11 @@ struct RkEpi {
 // [5][NP] (reference removed) sits at sm + el * PER + UO and its record (face
 // traces T, normal-gradient traces NN, edge traces) goes to sm + el * PER + XO.
 // Ends with a barrier.
-template <int N, typename R>
+template <int N, int PT, typename R>
 __device__ __forceinline__ void ns_trace_record(R *sm, int PER, int UO, int XO, int epb, int nb,
                                                 const NsOps<N, R> &op, int tid, int nth) {
-  constexpr int NP = N * N * N, NF = N * N;
+  constexpr int NPV = N * N * PT;                  // values per variable in the state layout
+  constexpr int NF = N * N;
   constexpr int FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
   // face traces and normal-gradient traces, face-major work items
   for (int t = tid; t < 6 * epb * NF; t += nth) {
@@ -372,13 +388,13 @@ __device__ __forceinline__ void ns_trace_record(R *sm, int PER, int UO, int XO, 
     auto item = [&](auto Dc, auto Sc) {
       constexpr int D = decltype(Dc)::value, S = decltype(Sc)::value, ff = 2 * D + S;
       int base, stride;
-      line_of<3, N>(D, q, base, stride);
+      ns_line<N, PT>(D, q, base, stride);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         R tr = R(0), nn = R(0);
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          R uv = u[v * NP + base + c * stride];
+          R uv = u[v * NPV + base + c * stride];
           tr += op.Lend[S][c] * uv;
           nn += op.rrow[S][c] * uv;
         }
@@ -463,7 +479,7 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
     }
   }
   __syncthreads();
-  ns_trace_record<N, R>(sm, PER, 0, pad4(5 * NP), epb, nb, op, tid, nth);
+  ns_trace_record<N, N, R>(sm, PER, 0, pad4(5 * NP), epb, nb, op, tid, nth);
   ns_store_records<N, R>(sm, PER, pad4(5 * NP), X, e0, nb, tid, nth);
 }
 
@@ -535,7 +551,13 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     const V *src = reinterpret_cast<const V *>(ch.in_r + (long long)e0 * 5 * NP);
     for (int t = tid; t < nb * 5 * NP / W; t += nth) {
       int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
-      *reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::U + r) = src[t];
+      const V x = src[t];
+      const R *xv = reinterpret_cast<const R *>(&x);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int rw = r + w;
+        sm[el * SM::TOTAL + SM::U + (rw / NP) * SM::NPP + ns_pidx<N, SM::PT>(rw % NP)] = xv[w];
+      }
     }
   } else {
     constexpr int W = (NP % 2 == 0) ? 2 : 1;
@@ -544,13 +566,13 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     for (int t = tid; t < nb * 5 * NP / W; t += nth) {
       int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
       double u0 = a.U0[r / NP];
-      R *dst = sm + el * SM::TOTAL + SM::U + r;
+      R *dst = sm + el * SM::TOTAL + SM::U + (r / NP) * SM::NPP;
       if constexpr (W == 2) {
         V x = src[t];
-        dst[0] = (R)(x.x - u0);
-        dst[1] = (R)(x.y - u0);
+        dst[ns_pidx<N, SM::PT>(r % NP)] = (R)(x.x - u0);
+        dst[ns_pidx<N, SM::PT>(r % NP + 1)] = (R)(x.y - u0);
       } else {
-        dst[0] = (R)(src[t] - u0);
+        dst[ns_pidx<N, SM::PT>(r % NP)] = (R)(src[t] - u0);
       }
     }
   }
@@ -598,9 +620,9 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
 #pragma unroll
       for (int c = 0; c < N; ++c) x[c] = R(0);
       if (ok) {
-        line_of<3, N>(m, q, base, stride);
+        ns_line<N, SM::PT>(m, q, base, stride);
 #pragma unroll
-        for (int c = 0; c < N; ++c) x[c] = E[SM::U + v * NP + base + c * stride];
+        for (int c = 0; c < N; ++c) x[c] = E[SM::U + v * SM::NPP + base + c * stride];
         tn0 = E[SM::TNN + ((2 * m) * 10 + v) * NF + q];
         tn1 = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + q];
         const R x0 = x[0];
@@ -615,7 +637,7 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
         const R th = (R)pick(m, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
 #pragma unroll
         for (int ai = 0; ai < N; ++ai)
-          E[SM::G + (m * 5 + v) * NP + base + ai * stride] =
+          E[SM::G + (m * 5 + v) * SM::NPP + base + ai * stride] =
               th * (y[ai] + R(0.5) * (op.Mc[0][ai] * tn0 + op.Mc[1][ai] * tn1));
       }
     }
@@ -627,18 +649,18 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     for (int m = 0; m < 3; ++m) {
       int am, qm, base, stride;
       coord_of<3, N>(pt, m, am, qm);
-      line_of<3, N>(m, qm, base, stride);
+      ns_line<N, SM::PT>(m, qm, base, stride);
       R th = (R)a.two_over_h[m];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const R *u = E + SM::U + v * NP + base;
+        const R *u = E + SM::U + v * SM::NPP + base;
         R acc = R(0);
 #pragma unroll
         for (int c = 0; c < N; ++c) acc += op.A[am][c] * u[c * stride];
         R tn0 = E[SM::TNN + ((2 * m) * 10 + v) * NF + qm];
         R tn1 = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + qm];
         acc += op.hMc[0][am] * tn0 + op.hMc[1][am] * tn1;
-        E[SM::G + (m * 5 + v) * NP + pt] = th * acc;
+        E[SM::G + (m * 5 + v) * SM::NPP + ns_pidx<N, SM::PT>(pt)] = th * acc;
       }
     }
   }
@@ -694,7 +716,7 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
 #pragma unroll
       for (int c = 0; c <= N; ++c) F[c] = R(0);
       if (ok) {
-        line_of<3, N>(d, q, base, stride);
+        ns_line<N, SM::PT>(d, q, base, stride);
         F[0] = E[SM::FH + ((2 * d) * 5 + v) * NF + q];
         F[N] = E[SM::FH + ((2 * d + 1) * 5 + v) * NF + q];
 #pragma unroll
@@ -708,7 +730,7 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
       if (ok) {
         const R thd = (R)pick(d, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
 #pragma unroll
-        for (int ai = 0; ai < N; ++ai) E[SM::G + (d * 5 + v) * NP + base + ai * stride] = -thd * y[ai];
+        for (int ai = 0; ai < N; ++ai) E[SM::G + (d * 5 + v) * SM::NPP + base + ai * stride] = -thd * y[ai];
       }
     }
   } else
@@ -726,8 +748,9 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
   __syncthreads();
   for (int t = tid; t < nb * 5 * NP; t += nth) {
     int el = t / (5 * NP), r = t % (5 * NP);
-    const R *E = sm + el * SM::TOTAL + SM::G;
-    double Rv = (double)E[r] + (double)E[5 * NP + r] + (double)E[10 * NP + r];
+    const int pr = (r / NP) * SM::NPP + ns_pidx<N, SM::PT>(r % NP);
+    const R *E = sm + el * SM::TOTAL + SM::G + pr;
+    double Rv = (double)E[0] + (double)E[5 * SM::NPP] + (double)E[10 * SM::NPP];
     long long i = (long long)e0 * 5 * NP + t;
     if (ep.mode == 0) {
       dudt[i] = Rv;
@@ -743,7 +766,7 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
           // region of LDS is dead here and takes it for the trace records
           const R wr = (R)(w - a.U0[r / NP]);
           ch.out_r[i] = wr;
-          sm[el * SM::TOTAL + SM::U + r] = wr;
+          sm[el * SM::TOTAL + SM::U + pr] = wr;
         } else {
           ep.out[i] = w;
         }
@@ -752,7 +775,7 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
   }
   if (ch.out_r) {
     __syncthreads();
-    ns_trace_record<N, R>(sm, SM::TOTAL, SM::U, SM::TNN, epb, nb, op, tid, nth);
+    ns_trace_record<N, SM::PT, R>(sm, SM::TOTAL, SM::U, SM::TNN, epb, nb, op, tid, nth);
     ns_store_records<N, R>(sm, SM::TOTAL, SM::TNN, ch.xnext, e0, nb, tid, nth);
   }
 }
