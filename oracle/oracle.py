@@ -43,15 +43,16 @@ class Params(ctypes.Structure):
         ("sutherland_s", ctypes.c_double),
         ("lambda_over_mu", ctypes.c_double),
         ("entropy_fix", ctypes.c_double),
+        ("eta_ip", ctypes.c_double),
     ]
 
 
 def make_params(physics="ns", nu=1.0, pme_m=2.0, gamma=1.4, Re=1600.0, Ma=0.1, Pr=0.71,
                 rho0=1.0, u0=1.0, Lref=1.0, sutherland_s=110.4 / 300.0,
-                lambda_over_mu=0.0, entropy_fix=0.1):
+                lambda_over_mu=0.0, entropy_fix=0.1, eta_ip=0.0):
     phys = {"diffusion": DIFFUSION, "pme": PME, "ns": NAVIER_STOKES}[physics]
     return Params(phys, nu, pme_m, gamma, Re, Ma, Pr, rho0, u0, Lref, sutherland_s,
-                  lambda_over_mu, entropy_fix)
+                  lambda_over_mu, entropy_fix, eta_ip)
 
 
 _lib = None
@@ -70,10 +71,10 @@ def lib():
         L.or_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         L.or_operators.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
         L.or_rhs_1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_rk4_1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
-                                ctypes.c_int]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp,
+                                ctypes.c_double, ctypes.c_int]
         L.or_rhs_3d.argtypes = [ip, dp, dp, ctypes.c_int, ctypes.c_int, pp, dp, dp, ctypes.c_int]
         L.or_rhs_3d_elems.argtypes = [ip, dp, dp, ctypes.c_int, ctypes.c_int, pp, dp, lp,
                                       ctypes.c_long, dp, ctypes.c_int]
@@ -122,20 +123,20 @@ def operators(p):
     return xs, ws, xf, L, M
 
 
-def rhs_1d(u, p, x0, x1, scheme="compact", physics="diffusion", coef=1.0):
+def rhs_1d(u, p, x0, x1, scheme="compact", physics="diffusion", coef=1.0, eta_ip=0.0):
     u = _f64(u)
     N = u.shape[0]
     out = np.zeros_like(u)
     phys = {"diffusion": DIFFUSION, "pme": PME}[physics]
-    _check(lib().or_rhs_1d(N, p, x0, x1, SCHEMES[scheme], phys, coef, _p(u), _p(out)), "rhs_1d")
+    _check(lib().or_rhs_1d(N, p, x0, x1, SCHEMES[scheme], phys, coef, eta_ip, _p(u), _p(out)), "rhs_1d")
     return out
 
 
-def rk4_1d(u, p, x0, x1, dt, nsteps, scheme="compact", physics="diffusion", coef=1.0):
+def rk4_1d(u, p, x0, x1, dt, nsteps, scheme="compact", physics="diffusion", coef=1.0, eta_ip=0.0):
     u = _f64(u).copy()
     phys = {"diffusion": DIFFUSION, "pme": PME}[physics]
-    _check(lib().or_rk4_1d(u.shape[0], p, x0, x1, SCHEMES[scheme], phys, coef, _p(u), dt, nsteps),
-           "rk4_1d")
+    _check(lib().or_rk4_1d(u.shape[0], p, x0, x1, SCHEMES[scheme], phys, coef, eta_ip, _p(u), dt,
+                           nsteps), "rk4_1d")
     return u
 
 

@@ -124,7 +124,7 @@ static double scalar_flux(int physics, double coef, double u, double v) {
 
 typedef struct {
   int N, n, scheme, physics;
-  double coef, J;
+  double coef, J, tau;
   double L[(OR_MAXN + 1) * OR_MAXN], M[OR_MAXN * (OR_MAXN + 1)];
   const double *u;
 } ctx1;
@@ -210,6 +210,15 @@ static void c1_rhs_elem(const ctx1 *c, int e, double *out) {
      eq. cmp:int:avg (compact); interior flux points keep v^F */
   vFC[0] = 0.5 * (c1_face_grad(c, e - 1, 1) + c1_face_grad(c, e, 0));
   vFC[n] = 0.5 * (c1_face_grad(c, e, 1) + c1_face_grad(c, e + 1, 0));
+  if (c->tau != 0.0) {
+    /* interior penalty (section 3): v_hat += tau (u_R - u_L) at each interface */
+    double a[OR_MAXN + 1], b[OR_MAXN + 1], d[OR_MAXN + 1];
+    c1_uF(c, e - 1, a);
+    c1_uF(c, e, b);
+    c1_uF(c, e + 1, d);
+    vFC[0] += c->tau * (b[0] - a[n]);
+    vFC[n] += c->tau * (d[0] - b[n]);
+  }
   /* flux G = F(u^{F,C}, v^{F,C}) at every flux point; at the interfaces
      this is option (a): G(H_hat, v_hat) */
   for (int i = 0; i <= n; ++i) G[i] = scalar_flux(c->physics, c->coef, HC[i], vFC[i]);
@@ -222,7 +231,7 @@ static void c1_rhs_elem(const ctx1 *c, int e, double *out) {
 }
 
 static int c1_setup(ctx1 *c, int N, int p, double x0, double x1, int scheme,
-                    int physics, double coef, const double *u) {
+                    int physics, double coef, double eta_ip, const double *u) {
   double xs[OR_MAXN], ws[OR_MAXN], xf[OR_MAXN + 1];
   if (N < 1 || p < 1 || p + 1 > OR_MAXN || !(x1 > x0)) return -1;
   if (scheme != OR_BR1 && scheme != OR_COMPACT) return -1;
@@ -230,33 +239,35 @@ static int c1_setup(ctx1 *c, int N, int p, double x0, double x1, int scheme,
   if (physics == OR_PME && (coef < 1.0 || coef != floor(coef))) return -1;
   c->N = N; c->n = p + 1; c->scheme = scheme; c->physics = physics; c->coef = coef;
   c->J = 0.5 * (x1 - x0) / N;      /* J_e = (x_{e+1} - x_e)/2, S_e = 1 */
+  if (!(eta_ip >= 0.0)) return -1;
+  c->tau = eta_ip * (double)(p + 1) * (double)(p + 1) / (2.0 * c->J);   /* h = element size */
   c->u = u;
   return or_operators(p, xs, ws, xf, c->L, c->M);
 }
 
 int or_rhs_1d(int N, int p, double x0, double x1, int scheme, int physics,
-              double coef, const double *u, double *dudt) {
+              double coef, double eta_ip, const double *u, double *dudt) {
   ctx1 c;
-  if (c1_setup(&c, N, p, x0, x1, scheme, physics, coef, u)) return -1;
+  if (c1_setup(&c, N, p, x0, x1, scheme, physics, coef, eta_ip, u)) return -1;
   for (int e = 0; e < N; ++e) c1_rhs_elem(&c, e, dudt + (long)e * c.n);
   return 0;
 }
 
 int or_rk4_1d(int N, int p, double x0, double x1, int scheme, int physics,
-              double coef, double *u, double dt, int nsteps) {
+              double coef, double eta_ip, double *u, double dt, int nsteps) {
   long sz = (long)N * (p + 1);
   double *k = malloc(sizeof(double) * sz * 5);
   if (!k) return -2;
   double *k1 = k, *k2 = k + sz, *k3 = k + 2 * sz, *k4 = k + 3 * sz, *w = k + 4 * sz;
   int rc = 0;
   for (int s = 0; s < nsteps && !rc; ++s) {
-    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, u, k1);
+    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, eta_ip, u, k1);
     for (long i = 0; i < sz; ++i) w[i] = u[i] + 0.5 * dt * k1[i];
-    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, w, k2);
+    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, eta_ip, w, k2);
     for (long i = 0; i < sz; ++i) w[i] = u[i] + 0.5 * dt * k2[i];
-    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, w, k3);
+    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, eta_ip, w, k3);
     for (long i = 0; i < sz; ++i) w[i] = u[i] + dt * k3[i];
-    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, w, k4);
+    rc |= or_rhs_1d(N, p, x0, x1, scheme, physics, coef, eta_ip, w, k4);
     for (long i = 0; i < sz; ++i)
       u[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
   }
@@ -623,10 +634,17 @@ static void c3_rhs_elem(const ctx3 *c, long e, double *out, work3 *w) {
     int ext[3];
     fam_ext(c, d, ext);
     long nf = (long)nv * ext[0] * ext[1] * ext[2];
+    /* interior penalty (section 3): the normal component gains
+       tau_d (u_R - u_L), tau_d = eta_ip (p+1)^2 / h_d */
+    const double tau = c->prm.eta_ip * (double)n * (double)n / c->h[d];
     for (int s = 0; s < 2; ++s) {
       long nb = c3_nbr(c, e, d, s);
       c3_face_grad(c, e, d, s, w->fg1, w->vS2, w->UF, w->tmp, w->H, w->dH);
       c3_face_grad(c, nb, d, 1 - s, w->fg2, w->vS2, w->UF, w->tmp, w->H, w->dH);
+      if (tau != 0.0) {
+        c3_uF(c, e, d, w->UFraw);
+        c3_uF(c, nb, d, w->UFnb);
+      }
       int end = s == 0 ? 0 : n;
       for (int m = 0; m < 3; ++m)
         for (int v = 0; v < nv; ++v)
@@ -638,7 +656,15 @@ static void c3_rhs_elem(const ctx3 *c, long e, double *out, work3 *w) {
               /* left element's value first, as in eq. cmp:int:avg */
               double lv = s == 0 ? w->fg2[f] : w->fg1[f];
               double rv = s == 0 ? w->fg1[f] : w->fg2[f];
-              w->VF[d][m * nf + aidx(ext, v, id[0], id[1], id[2])] = 0.5 * (lv + rv);
+              double vh = 0.5 * (lv + rv);
+              if (tau != 0.0 && m == d) {
+                int io[3] = {id[0], id[1], id[2]};
+                io[d] = s == 0 ? n : 0;              /* the neighbour's end */
+                double uo = w->UFraw[aidx(ext, v, id[0], id[1], id[2])];
+                double un = w->UFnb[aidx(ext, v, io[0], io[1], io[2])];
+                vh += tau * (s == 0 ? uo - un : un - uo);
+              }
+              w->VF[d][m * nf + aidx(ext, v, id[0], id[1], id[2])] = vh;
             }
     }
   }
@@ -709,6 +735,7 @@ static int c3_setup(ctx3 *c, const int *nel, const double *lo, const double *hi,
     c->nel[d] = nel[d];
     c->h[d] = (hi[d] - lo[d]) / nel[d];
   }
+  if (!(prm->eta_ip >= 0.0)) return -1;
   c->n = p + 1;
   c->scheme = scheme;
   c->prm = *prm;

@@ -41,6 +41,11 @@ typedef struct {
                              temperature; a negative value means constant mu */
   double lambda_over_mu;  /* second viscosity coefficient over mu            */
   double entropy_fix;     /* Harten delta = entropy_fix * (|u_n| + c)        */
+  double eta_ip;          /* interior penalty (section 3): the normal
+                             component of the common gradient at an
+                             interface gains tau (u_R - u_L), tau =
+                             eta_ip (p+1)^2 / h, h the element size normal
+                             to the interface; 0 = off                       */
 } or_params;
 
 /* Gauss-Legendre nodes (ascending) and weights on [-1, 1]. */
@@ -51,13 +56,14 @@ int or_gauss_legendre(int n, double *x, double *w);
 int or_operators(int p, double *xs, double *ws, double *xf, double *L, double *M);
 
 /* 1-D semi-discrete RHS du/dt for u[N][n] on the periodic [x0, x1].
- * physics: OR_DIFFUSION (coef = nu) or OR_PME (coef = m). */
+ * physics: OR_DIFFUSION (coef = nu) or OR_PME (coef = m); eta_ip: interior
+ * penalty coefficient (0 = off), as in or_params. */
 int or_rhs_1d(int N, int p, double x0, double x1, int scheme, int physics,
-              double coef, const double *u, double *dudt);
+              double coef, double eta_ip, const double *u, double *dudt);
 
 /* Classical RK4 for the 1-D problem, nsteps steps of size dt, in place. */
 int or_rk4_1d(int N, int p, double x0, double x1, int scheme, int physics,
-              double coef, double *u, double dt, int nsteps);
+              double coef, double eta_ip, double *u, double dt, int nsteps);
 
 /* 3-D semi-discrete RHS on a periodic nel[0] x nel[1] x nel[2] box.
  * Scalar physics (diffusion, PME) has one variable, Navier-Stokes five.
