@@ -83,6 +83,12 @@ typedef struct {
                              p0/(gamma-1)) before the contractions (exact
                              algebra: L reproduces constants, M annihilates
                              them); -1: automatic (on unless FP64)          */
+  double eta_ip;          /* interior penalty (section 3): the normal
+                             component of the common gradient at every
+                             interface gains tau (u_R - u_L),
+                             tau = eta_ip (p+1)^2 / h, h the element size
+                             normal to the interface; 0 (default) = off,
+                             negative or non-finite = SD_EINVAL             */
 } sd_params;
 
 typedef struct {

@@ -71,6 +71,7 @@ struct KArgs {
   double cp_over_pr;     // kappa / mu = gamma / ((gamma - 1) Pr), R = 1
   double efix;           // Harten coefficient
   double U0[5];          // subtracted constant state per variable
+  double tau[3];         // interior penalty eta_ip (p+1)^2 / h_d (0: off)
 };
 
 // Face / edge bookkeeping of the trace buffer (per element, in elements of

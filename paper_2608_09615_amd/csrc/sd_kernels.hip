@@ -269,7 +269,13 @@ __global__ void __launch_bounds__(256) k_rhs(const double *__restrict__ U, const
         voth = R(0);
       }
     }
-    S(el, SM::VH)[r] = s == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
+    R vh = s == 0 ? R(0.5) * (voth + vown) : R(0.5) * (vown + voth);
+    if (m == d) {
+      // interior penalty on the normal component: tau_d (u_R - u_L)
+      R own = S(el, SM::TO)[fv], oth = S(el, SM::TN)[fv];
+      vh += (R)a.tau[d] * (s == 0 ? own - oth : oth - own);
+    }
+    S(el, SM::VH)[r] = vh;
   }
   __syncthreads();
   // E: per family d, fluxes at the n+1 flux points of every line, then the

@@ -239,6 +239,22 @@ __device__ __forceinline__ void ns_face_item(const KArgs &a, const NsOps<N, R> &
   R F[5];
   if constexpr (PART == 1) {
     ns_roe(c, UL, UR, D, F);
+    if (a.tau[D] != 0.0) {
+      // interior penalty on the normal component of the common gradient,
+      // tau_D (U_R - U_L): the viscous flux is linear in the gradient for a
+      // given state, so its share is F_v(U_hat, penalty) (added here, where
+      // few registers are live, rather than in the viscous pass)
+      R Gp[15];
+#pragma unroll
+      for (int w = 0; w < 15; ++w) Gp[w] = R(0);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Gp[D * 5 + v] = (R)a.tau[D] * (UR[v] - UL[v]);
+      Prim<R> sp = ns_prim(c, Uh);
+      R Fp[5];
+      ns_visc(c, sp, Gp, D, Fp);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= Fp[v];
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) E[SM::FH + (f * 5 + v) * NF + q] += F[v];
     return;

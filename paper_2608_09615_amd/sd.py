@@ -49,6 +49,7 @@ class Params(ctypes.Structure):
         ("entropy_fix", ctypes.c_double),
         ("precision", ctypes.c_int),
         ("ref_state", ctypes.c_int),
+        ("eta_ip", ctypes.c_double),
     ]
 
 

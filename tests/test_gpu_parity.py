@@ -253,3 +253,55 @@ def test_tgv_32cubed_sampled_parity(torch_cuda, oracle_lib):
             err = relerr(R[sel], Ro)
             print(f"32^3 {scheme} {precision}: error {err:.3e} (ulp sensitivity {sens:.3e})")
             assert err < tol, (scheme, precision, err, sens)
+
+
+# ---------------------------------------------------------------------------
+# Interior-penalty variant (section 3): the normal component of the common
+# gradient gains tau (u_R - u_L), tau = eta_IP (p+1)^2 / h.
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("physics", ["diffusion", "pme"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ip_1d_parity(torch_cuda, oracle_lib, scheme, physics, precision):
+    p, N, eta = 3, 11, 0.5
+    coef = 1.0 if physics == "diffusion" else 2.0
+    u = 1.0 + 0.3 * np.random.Generator(np.random.PCG64(12)).uniform(-1, 1, (N, p + 1))
+    kw = dict(nu=coef) if physics == "diffusion" else dict(pme_m=coef)
+    R, _ = gpu_rhs(torch_cuda, u[:, None, :], [N], p, scheme, physics, precision, [-1.0], [2.0], eta_ip=eta, **kw)
+    Ro = oracle_lib.rhs_1d(u, p, -1.0, 2.0, scheme=scheme, physics=physics, coef=coef, eta_ip=eta)
+    R0 = oracle_lib.rhs_1d(u, p, -1.0, 2.0, scheme=scheme, physics=physics, coef=coef)
+    err = relerr(R, Ro[:, None, :])
+    print(f"IP 1-D {physics} {scheme} {precision}: {err:.3e} (IP changes R by {relerr(R0[:, None, :], Ro[:, None, :]):.2e})")
+    assert err < (FP64_TOL if precision == "fp64" else FP32_TOL_SCALAR)
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_ip_3d_diffusion_parity(torch_cuda, oracle_lib, scheme):
+    p, nel, eta = 2, (3, 2, 4), 0.5
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 2.0, 1.5)
+    U = W.random_scalar_3d(nel, p, seed=4)
+    R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "diffusion", "fp64", lo, hi, nu=0.8, eta_ip=eta)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, oracle_lib.make_params("diffusion", nu=0.8, eta_ip=eta))
+    assert relerr(R, Ro) < FP64_TOL
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_ip_ns_parity(torch_cuda, oracle_lib, scheme, p):
+    """NS with the penalty in FP64, FP32 and BF16x3.  The penalty takes the
+    jump of two traces of rho E ~ 180 that differ by ~1e-3, so the RHS
+    inherits the FP64 rounding of the traces: the FP64 bar is
+    max(1e-12, 4 x the oracle's one-ulp sensitivity)."""
+    nel, eta = (3, 4, 2), 1.0
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns", Re=400.0, eta_ip=eta)
+    U = W.perturbed_tgv_state(nel, p, seed=40 + p, noise=1e-3)
+    sel = np.arange(int(np.prod(nel)))
+    Ro, sens = ulp_sensitivity(oracle_lib, U, nel, lo, hi, p, scheme, prm, sel)
+    R0 = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, oracle_lib.make_params("ns", Re=400.0))
+    assert relerr(R0, Ro) > 1e-4                      # the penalty acts
+    for precision, tol in (("fp64", max(FP64_TOL, 4 * sens)), ("fp32", FP32_TOL_NS), ("bf16x3", BF16X3_TOL_NS)):
+        R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", precision, lo, hi, Re=400.0, eta_ip=eta)
+        err = relerr(R, Ro)
+        print(f"IP NS p={p} {scheme} {precision}: {err:.3e} (ulp sensitivity {sens:.2e})")
+        assert err < tol, (precision, err, sens)
