@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--scheme", default="compact")
     ap.add_argument("--Re", type=float, default=1600.0)
+    ap.add_argument("--eta-ip", type=float, default=0.0, help="interior-penalty coefficient (0: off)")
     ap.add_argument("--ke-steps", type=int, default=150, help="RK4 steps of the FP32-vs-FP64 KE check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
@@ -64,7 +65,7 @@ def measured_traffic(args, precision):
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "rhs_traffic_tgv32p3.json")
-    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and os.path.exists(path)):
+    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip and os.path.exists(path)):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -83,7 +84,7 @@ def run_path(torch, W, args, precision, U0, dt):
     lo, hi = W.tgv_domain()
     nel = (args.nel,) * 3
     sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi,
-            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4)
+            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4, eta_ip=args.eta_ip)
     u = torch.from_numpy(U0).to("cuda")
     for _ in range(args.warmup):
         sd.rk_step(u, dt)
@@ -228,7 +229,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"TGV Re={args.Re:g} Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}",
+        "config": {"workload": f"TGV Re={args.Re:g} Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}"
+                               + (f" eta_ip={args.eta_ip:g}" if args.eta_ip else ""),
                    "dof": dof, "step": "one RK4 step = 4 RHS + 4 FP64 stage updates",
                    "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
         "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "fp32"),
