@@ -4,8 +4,9 @@ Workload: compressible Navier-Stokes Taylor-Green vortex, Re = 1600, Ma = 0.1,
 Pr = 0.71, gamma = 1.4 on the periodic box [0, 2 pi]^3 with 32^3 hexahedra
 at p = 3 (2 097 152 solution points, 5 conserved variables), compact scheme.
 One bench step is one classical RK4 step: four right-hand sides and four FP64
-stage updates on the device-resident state.  The metric counts solution
-points (DOF) per RK stage: GDOF/s = n_el (p+1)^3 * 4 * steps / time.
+stage updates on the device-resident state (``--integrator ssprk54``: five
+right-hand sides and five FP64 combinations).  The metric counts solution
+points (DOF) per RK stage: GDOF/s = n_el (p+1)^3 * stages * steps / time.
 
 Prints one JSON line.  ``value`` is the FP32 path (contractions and fluxes in
 FP32, reference state removed, FP64 RK accumulation); the FP64 path is timed
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--scheme", default="compact")
     ap.add_argument("--Re", type=float, default=1600.0)
     ap.add_argument("--eta-ip", type=float, default=0.0, help="interior-penalty coefficient (0: off)")
+    ap.add_argument("--integrator", default="rk4", choices=["rk4", "ssprk54"],
+                    help="rk4: 4 RHS per step; ssprk54: 5 RHS per step (section 4.4's scheme)")
     ap.add_argument("--ke-steps", type=int, default=150, help="RK4 steps of the FP32-vs-FP64 KE check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
@@ -65,7 +68,8 @@ def measured_traffic(args, precision):
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "rhs_traffic_tgv32p3.json")
-    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip and os.path.exists(path)):
+    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip
+            and args.integrator == "rk4" and os.path.exists(path)):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -84,7 +88,7 @@ def run_path(torch, W, args, precision, U0, dt):
     lo, hi = W.tgv_domain()
     nel = (args.nel,) * 3
     sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision=precision, lo=lo, hi=hi,
-            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4, eta_ip=args.eta_ip)
+            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4, eta_ip=args.eta_ip, integrator=args.integrator)
     u = torch.from_numpy(U0).to("cuda")
     for _ in range(args.warmup):
         sd.rk_step(u, dt)
@@ -102,7 +106,7 @@ def run_path(torch, W, args, precision, U0, dt):
     ne = args.nel ** 3
     dof = ne * (args.p + 1) ** 3
     sec = t1 - t0
-    stages = 4 * args.steps
+    stages = (5 if args.integrator == "ssprk54" else 4) * args.steps
     out = {
         "gdofs": dof * stages / sec / 1e9,
         "ms_per_step": 1e3 * sec / args.steps,
@@ -231,7 +235,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"TGV Re={args.Re:g} Ma=0.1 {args.nel}^3 hex p={args.p} {args.scheme}"
                                + (f" eta_ip={args.eta_ip:g}" if args.eta_ip else ""),
-                   "dof": dof, "step": "one RK4 step = 4 RHS + 4 FP64 stage updates",
+                   "dof": dof,
+                   "step": ("one SSP-RK(5,4) step = 5 RHS + 5 FP64 stage combinations" if args.integrator == "ssprk54"
+                            else "one RK4 step = 4 RHS + 4 FP64 stage updates"),
                    "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
         "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "fp32"),
         "fp64": {"value": r64["gdofs"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",

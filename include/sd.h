@@ -57,6 +57,11 @@ typedef enum { SD_DIFFUSION = 0, SD_PME = 1, SD_NAVIER_STOKES = 2 } sd_physics;
 /* Arithmetic of the contractions and fluxes.  The public state, the RHS and
  * the RK accumulation stay FP64 in every mode. */
 typedef enum { SD_FP64 = 0, SD_FP32 = 1, SD_BF16X3 = 2 } sd_precision;
+/* Time integrator of sd_rk_step: classical RK4 (4 stages), or the
+ * five-stage, fourth-order strong-stability-preserving scheme of Spiteri and
+ * Ruuth that section 4.4 integrates the TGV with (Shu-Osher form, published
+ * coefficients; the paper does not print them). */
+typedef enum { SD_RK4 = 0, SD_SSPRK54 = 1 } sd_integrator;
 
 /* Uniform periodic Cartesian mesh: dim 1 uses nelem[0], lo[0], hi[0] only. */
 typedef struct {
@@ -89,6 +94,7 @@ typedef struct {
                              tau = eta_ip (p+1)^2 / h, h the element size
                              normal to the interface; 0 (default) = off,
                              negative or non-finite = SD_EINVAL             */
+  int integrator;         /* sd_integrator of sd_rk_step (default SD_RK4)    */
 } sd_params;
 
 typedef struct {
@@ -131,8 +137,11 @@ long long sd_state_size(const sd_ctx *ctx);
  * not overlap.  u is read only. */
 int sd_rhs(sd_ctx *ctx, const double *u, double *dudt);
 
-/* One classical fourth-order Runge-Kutta step of size dt, in place on the
- * device state u; stage states and the accumulation are FP64. */
+/* One time step of size dt, in place on the device state u, with the
+ * integrator of sd_params.integrator (classical RK4, or SSP-RK(5,4)); the
+ * stage combinations and the accumulation are FP64 (with RK4 in FP32 or
+ * BF16x3, the intermediate stage states are kept as the compute-precision
+ * values the RHS would round them to). */
 int sd_rk_step(sd_ctx *ctx, double *u, double dt);
 
 /* Diagnostics of a Navier-Stokes state (FP64 reductions, deterministic):

@@ -364,6 +364,25 @@ __global__ void k_rk_final(double *__restrict__ u, const double *__restrict__ k4
   u[i] = u[i] + dt6 * (acc[i] + k4[i]);
 }
 
+// SSP-RK(5,4) combinations (Shu-Osher form): out = a0 x0 + a1 x1 + b k
+__global__ void k_lincomb(const double *__restrict__ x0, const double *__restrict__ x1,
+                          const double *__restrict__ k, double *__restrict__ out, double a0, double a1, double b,
+                          long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a0 * x0[i] + a1 * x1[i] + b * k[i];
+}
+
+// last SSP-RK(5,4) stage: out = a2 u2 + a3 u3 + b3 L3 + a4 u4 + b4 L4
+__global__ void k_ssp_final(const double *__restrict__ u2, const double *__restrict__ u3,
+                            const double *__restrict__ L3, const double *__restrict__ u4,
+                            const double *__restrict__ L4, double *__restrict__ out, double a2, double a3,
+                            double b3, double a4, double b4, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a2 * u2[i] + a3 * u3[i] + b3 * L3[i] + a4 * u4[i] + b4 * L4[i];
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics (FP64): per block partial sums of the Gauss-quadrature
 // integrals, then one block sums the partials in a fixed order.

@@ -14,6 +14,7 @@ SD_OK, SD_EINVAL, SD_ENOMEM, SD_EHIP, SD_ENONFINITE, SD_EUNSUPPORTED = 0, -1, -2
 SCHEMES = {"br1": 0, "compact": 1}
 PHYSICS = {"diffusion": 0, "pme": 1, "ns": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
            "sd_rk_step", "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_last_error",
@@ -50,6 +51,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("ref_state", ctypes.c_int),
         ("eta_ip", ctypes.c_double),
+        ("integrator", ctypes.c_int),
     ]
 
 
@@ -124,7 +126,8 @@ class SD:
     ``nelem``: elements per direction (length 1 or 3); ``p``: degree;
     ``scheme``: "compact" or "br1"; ``physics``: "diffusion", "pme" or "ns";
     ``precision``: "fp64", "fp32" or "bf16x3".  Extra keyword arguments set
-    the fields of ``sd_params`` (nu, pme_m, gamma, Re, Ma, Pr, ...).
+    the fields of ``sd_params`` (nu, pme_m, gamma, Re, Ma, Pr, eta_ip,
+    integrator = "rk4" or "ssprk54", ...).
     """
 
     def __init__(self, nelem, p, scheme="compact", physics="ns", precision="fp64", lo=None, hi=None,
@@ -144,6 +147,8 @@ class SD:
         _check(L.sd_params_default(ctypes.byref(prm)))
         prm.physics = PHYSICS[physics]
         prm.precision = PRECISIONS[precision]
+        if isinstance(params.get("integrator"), str):
+            params["integrator"] = INTEGRATORS[params["integrator"]]
         for k, v in params.items():
             if not hasattr(prm, k):
                 raise TypeError(f"unknown parameter {k}")

@@ -24,12 +24,14 @@ def step_size(nel, p, dt_out, Ma=0.1, cfl=0.3):
     return dt_out / k, k
 
 
-def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, dt_out=0.1, log=print):
+def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, dt_out=0.1, log=print,
+            integrator="rk4"):
     """KE and enstrophy every dt_out up to t_end, and the wall time of the
     stepping (diagnostics included)."""
     import torch
     lo, hi = W.tgv_domain()
-    sd = SD((nel,) * 3, p, scheme=scheme, physics="ns", precision=precision, lo=lo, hi=hi, Re=Re, Ma=0.1, Pr=0.71)
+    sd = SD((nel,) * 3, p, scheme=scheme, physics="ns", precision=precision, lo=lo, hi=hi, Re=Re, Ma=0.1, Pr=0.71,
+            integrator=integrator)
     u = torch.from_numpy(W.tgv_state((nel,) * 3, p)).to("cuda")
     dt, k = step_size(nel, p, dt_out)
     nout = int(round(t_end / dt_out))
@@ -52,7 +54,8 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sd.close()
-    return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "dt": dt, "steps": nout * k,
+    return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "integrator": integrator,
+            "dt": dt, "steps": nout * k,
             "t": t, "ke": ke, "enstrophy": ens, "wall_s": wall}
 
 
@@ -73,10 +76,12 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=20.0)
     ap.add_argument("--dt-out", type=float, default=0.1)
     ap.add_argument("--precisions", default="fp64,fp32", help="the first one is the reference")
+    ap.add_argument("--integrator", default="rk4", choices=["rk4", "ssprk54"])
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
-    runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log) for pr in a.precisions.split(",")]
+    runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log, a.integrator)
+            for pr in a.precisions.split(",")]
     res = {"runs": runs, "errors": {r["precision"]: compare(r, runs[0]) for r in runs[1:]}}
     for r in runs[1:]:
         log(f"tgv: {r['precision']} vs {runs[0]['precision']}: {json.dumps(res['errors'][r['precision']])}")

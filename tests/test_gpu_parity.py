@@ -305,3 +305,53 @@ def test_ip_ns_parity(torch_cuda, oracle_lib, scheme, p):
         err = relerr(R, Ro)
         print(f"IP NS p={p} {scheme} {precision}: {err:.3e} (ulp sensitivity {sens:.2e})")
         assert err < tol, (precision, err, sens)
+
+
+# ---------------------------------------------------------------------------
+# SSP-RK(5,4) (section 4.4's integrator) against the reference integrator.
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_ssprk54_step_parity(torch_cuda, oracle_lib, scheme, precision):
+    from oracle import ssprk
+    from paper_2608_09615_amd import SD
+    nel, p = (3, 3, 4), 3
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns")
+    U = W.perturbed_tgv_state(nel, p, seed=9, noise=1e-3)
+    print(f"[ssprk54] {scheme} {precision}", flush=True)
+    sd = SD(nel, p, scheme=scheme, physics="ns", precision=precision, lo=lo, hi=hi, integrator="ssprk54")
+    u = torch_cuda.from_numpy(U).to("cuda")
+    dt = 2e-3
+    for _ in range(2):
+        sd.rk_step(u, dt)
+    got = u.cpu().numpy()
+    sd.close()
+    ref = ssprk.integrate(lambda x: oracle_lib.rhs_3d(x, nel, lo, hi, p, scheme, prm), U, dt, 2)
+    change = np.abs(ref - U).max()
+    err = np.abs(got - ref).max() / change
+    print(f"ssprk54 {scheme} {precision}: {err:.3e} relative to the change {change:.3e}")
+    # The Shu-Osher stages are convex combinations of whole states (rho E ~ 180),
+    # so each of the 2 x 5 combinations rounds at the scale of |U|, not of the
+    # change (~0.04 here): the device evaluates them with fused multiply-adds,
+    # the oracle term by term.  Allow one ulp of max|U| per combination and
+    # side on top of the 1e-12 relative bar (~2e-11 of the change here); a
+    # coefficient wrong in its 12th digit still moves the result by more.
+    floor = 2 * 10 * np.finfo(np.float64).eps * np.abs(U).max() / change
+    assert err < (max(1e-12, floor) if precision == "fp64" else FP32_TOL_NS)
+
+
+def test_ssprk54_1d_diffusion_parity(torch_cuda, oracle_lib):
+    from oracle import ssprk
+    from paper_2608_09615_amd import SD
+    p, N = 4, 9
+    u0 = np.random.Generator(np.random.PCG64(19)).normal(size=(N, p + 1))
+    sd = SD([N], p, scheme="compact", physics="diffusion", lo=[0.0], hi=[2.0], nu=0.6, integrator="ssprk54")
+    u = torch_cuda.from_numpy(u0[:, None, :].copy()).to("cuda")
+    dt = 1e-4
+    for _ in range(3):
+        sd.rk_step(u, dt)
+    got = u.cpu().numpy()[:, 0, :]
+    sd.close()
+    ref = ssprk.integrate(lambda x: oracle_lib.rhs_1d(x, p, 0.0, 2.0, scheme="compact", coef=0.6), u0, dt, 3)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref - u0).max()

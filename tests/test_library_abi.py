@@ -75,6 +75,7 @@ def _init(lib, dim=3, nel=(4, 4, 4), p=3, scheme=1, **kw):
     (dict(Re=-1.0), -1),
     (dict(eta_ip=-0.5), -1),
     (dict(eta_ip=float("nan")), -1),
+    (dict(integrator=7), -1),
 ])
 def test_invalid_arguments_are_rejected(lib, kw, code):
     rc, msg = _init(lib, **kw)
@@ -87,6 +88,7 @@ def test_params_default_values(lib):
     assert lib.sd_params_default(ctypes.byref(prm)) == 0
     assert prm.physics == 2 and prm.gamma == 1.4 and prm.Re == 1600.0 and prm.Ma == 0.1
     assert prm.Pr == 0.71 and prm.lambda_over_mu == 0.0 and prm.ref_state == -1 and prm.eta_ip == 0.0
+    assert prm.integrator == 0
     assert lib.sd_params_default(None) == -1
 
 
