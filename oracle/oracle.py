@@ -178,11 +178,11 @@ def rk4_3d(u, nel, lo, hi, p, scheme, params, dt, nsteps, nthreads=0):
 
 def diag_3d(u, nel, lo, hi, p, params, nthreads=0):
     u = _f64(u)
-    out = np.zeros(9)
+    out = np.zeros(10)
     nel_a, lo_a, hi_a = _mesh(nel, lo, hi)
     _check(lib().or_diag_3d(nel_a, _p(lo_a), _p(hi_a), p, ctypes.byref(params), _p(u), _p(out),
                             nthreads), "diag_3d")
-    keys = ["ke", "enstrophy", "mass", "mom0", "mom1", "mom2", "energy", "umax", "nonfinite"]
+    keys = ["ke", "enstrophy", "mass", "mom0", "mom1", "mom2", "energy", "umax", "nonfinite", "smax"]
     return dict(zip(keys, out.tolist()))
 
 

@@ -828,11 +828,11 @@ int or_diag_3d(const int *nel, const double *lo, const double *hi, int p,
   long ne = (long)nel[0] * nel[1] * nel[2];
   int n = c.n;
   long n3 = (long)n * n * n;
-  double ke = 0, ens = 0, mass = 0, m0 = 0, m1 = 0, m2 = 0, en = 0, umax = 0;
+  double ke = 0, ens = 0, mass = 0, m0 = 0, m1 = 0, m2 = 0, en = 0, umax = 0, smax = 0;
   int bad = 0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel reduction(+ : ke, ens, mass, m0, m1, m2, en) reduction(max : umax) \
+#pragma omp parallel reduction(+ : ke, ens, mass, m0, m1, m2, en) reduction(max : umax, smax) \
     reduction(| : bad)
 #endif
   {
@@ -871,12 +871,17 @@ int or_diag_3d(const int *nel, const double *lo, const double *hi, int p,
               m2 += wq * U[3];
               en += wq * U[4];
               if (sqrt(v2) > umax) umax = sqrt(v2);
+              /* fastest acoustic signal |u| + c, c^2 = gamma P / rho (the
+                 convective time-step limit of section 4.4) */
+              double P = (prm->gamma - 1.0) * (U[4] - 0.5 * U[0] * v2);
+              double sp = (U[0] > 0.0 && P >= 0.0) ? sqrt(v2) + sqrt(prm->gamma * P / U[0]) : INFINITY;
+              if (sp > smax) smax = sp;
             }
       }
       free(w.UF);
     }
   }
   out[0] = ke; out[1] = ens; out[2] = mass; out[3] = m0; out[4] = m1; out[5] = m2;
-  out[6] = en; out[7] = umax; out[8] = (bad & 1) ? 1.0 : 0.0;
+  out[6] = en; out[7] = umax; out[8] = (bad & 1) ? 1.0 : 0.0; out[9] = smax;
   return (bad & 2) ? -2 : 0;
 }

@@ -86,7 +86,8 @@ int or_rk4_3d(const int *nel, const double *lo, const double *hi, int p,
 
 /* Diagnostics of a Navier-Stokes state: out[0] kinetic energy, out[1]
  * enstrophy, out[2] mass, out[3..5] momentum, out[6] total energy,
- * out[7] max |u|, out[8] 1 if any value is non-finite. */
+ * out[7] max |u|, out[8] 1 if any value is non-finite, out[9] max(|u| + c)
+ * with c = sqrt(gamma P / rho), infinite if rho <= 0 or P < 0 anywhere. */
 int or_diag_3d(const int *nel, const double *lo, const double *hi, int p,
                const or_params *prm, const double *u, double *out,
                int nthreads);

@@ -129,6 +129,33 @@ def test_tgv_initial_diagnostics(oracle_lib):
     assert d["nonfinite"] == 0.0 and abs(d["umax"] - 1.0) < 0.05
 
 
+def test_signal_speed(oracle_lib):
+    """max(|u| + c), c = sqrt(gamma P / rho): a uniform state gives the closed
+    form; the TGV state gives the maximum taken over the primitive fields
+    (the oracle goes through the conservative variables); an inadmissible
+    state (negative pressure at one point) gives +inf."""
+    lo, hi = W.tgv_domain()
+    nel, p = (3, 2, 2), 2
+    shape = (12, 3, 3, 3)
+    for gamma in (1.4, 5.0 / 3.0):
+        prm = oracle_lib.make_params("ns", gamma=gamma)
+        one = np.ones(shape)
+        U = W.conservative(1.3 * one, 0.2 * one, -0.5 * one, 0.1 * one, 2.0 * one, gamma=gamma)
+        d = oracle_lib.diag_3d(U, nel, lo, hi, p, prm)
+        assert abs(d["smax"] - (math.sqrt(0.3) + math.sqrt(gamma * 2.0 / 1.3))) < 1e-14
+    prm = oracle_lib.make_params("ns")
+    nel, p = (4, 4, 4), 3
+    X, Y, Z = W.points_3d(nel, lo, hi, p)
+    rho, u, v, w, pr = W.tgv_primitive(X, Y, Z)
+    expect = np.max(np.sqrt(u * u + v * v + w * w) + np.sqrt(1.4 * pr / rho))
+    d = oracle_lib.diag_3d(W.tgv_state(nel, p), nel, lo, hi, p, prm)
+    assert abs(d["smax"] - expect) < 1e-13 * expect
+    assert 10.0 < d["smax"] < 11.1            # c0 = u0 / Ma = 10, |u| <= 1
+    U = W.tgv_state(nel, p)
+    U[5, 4, 1, 2, 3] = 0.0                    # rho E = 0 with u != 0 there: P < 0
+    assert oracle_lib.diag_3d(U, nel, lo, hi, p, prm)["smax"] == math.inf
+
+
 def test_tgv_initial_dissipation_rate(oracle_lib):
     """dE_k/dt at t = 0 is -nu * enstrophy up to O(Ma^2) and discretisation
     error (kinetic-energy balance of the viscous term)."""
