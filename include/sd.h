@@ -105,6 +105,8 @@ typedef struct {
   double energy;     /* int rho E dV                                        */
   double umax;       /* max |u| over the solution points                    */
   int nonfinite;     /* 1 if any state value is NaN or infinite             */
+  double smax;       /* max (|u| + c) over the solution points, c^2 =
+                        gamma P / rho; +inf if rho <= 0 or P < 0 anywhere  */
 } sd_diag;
 
 typedef struct sd_ctx sd_ctx;
@@ -148,6 +150,15 @@ int sd_rk_step(sd_ctx *ctx, double *u, double dt);
  * waits for the stream and fills the host struct *out.  Returns
  * SD_ENONFINITE (with *out filled) when the state holds NaN or Inf. */
 int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
+
+/* Largest stable time step of a Navier-Stokes state for the convective
+ * limit (section 4.4's TGV runs): *dt = cfl * min_d h_d / ((p + 1) smax),
+ * smax from sd_diagnostics of u (this call waits for the stream).  cfl is
+ * the Courant number (0.3 in the TGV runs; > 0 and finite, else SD_EINVAL).
+ * The viscous limit is not included.  Returns SD_ENONFINITE, *dt untouched,
+ * when the state is non-finite, has rho <= 0 or P < 0 somewhere, or has no
+ * positive signal speed; SD_EUNSUPPORTED for scalar physics. */
+int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
 
 /* Timing of the right-hand side kernels: with enable = 1 every later RHS
  * evaluation of the context (sd_rhs and the four inside sd_rk_step) is

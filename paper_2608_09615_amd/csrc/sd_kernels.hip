@@ -387,7 +387,8 @@ __global__ void k_ssp_final(const double *__restrict__ u2, const double *__restr
 // Diagnostics (FP64): per block partial sums of the Gauss-quadrature
 // integrals, then one block sums the partials in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kDiagVals = 9;  // ke, ens, mass, mom0..2, energy, umax, bad
+constexpr int kDiagVals = 10;  // ke, ens, mass, mom0..2, energy, umax, bad, smax
+__host__ __device__ constexpr bool diag_is_max(int c) { return c >= 7; }
 
 template <int N>
 __global__ void __launch_bounds__(256) k_diag(const double *__restrict__ U, const double *__restrict__ X,
@@ -424,7 +425,7 @@ __global__ void __launch_bounds__(256) k_diag(const double *__restrict__ U, cons
     sG[t] = a.two_over_h[m] * acc;
   }
   __syncthreads();
-  double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < nb * NP; t += blockDim.x) {
     int el = t / NP, pt = t % NP;
     int i = pt % N, j = (pt / N) % N, k = pt / (N * N);
@@ -451,6 +452,11 @@ __global__ void __launch_bounds__(256) k_diag(const double *__restrict__ U, cons
     acc[5] += wq * Uq[3];
     acc[6] += wq * Uq[4];
     acc[7] = fmax(acc[7], sqrt(v2));
+    // fastest acoustic signal |u| + c, c^2 = gamma P / rho
+    // (infinite where the state is inadmissible: rho <= 0 or P < 0)
+    const double P = a.gm1 * (Uq[4] - 0.5 * Uq[0] * v2);
+    const double sp = (Uq[0] > 0.0 && P >= 0.0) ? sqrt(v2) + sqrt((a.gm1 + 1.0) * P / Uq[0]) : HUGE_VAL;
+    acc[9] = fmax(acc[9], sp);
   }
   for (int c = 0; c < kDiagVals; ++c) red[threadIdx.x * kDiagVals + c] = acc[c];
   __syncthreads();
@@ -459,7 +465,7 @@ __global__ void __launch_bounds__(256) k_diag(const double *__restrict__ U, cons
       for (int c = 0; c < kDiagVals; ++c) {
         double o = red[(threadIdx.x + w) * kDiagVals + c];
         double &m = red[threadIdx.x * kDiagVals + c];
-        m = (c == 7 || c == 8) ? fmax(m, o) : m + o;
+        m = diag_is_max(c) ? fmax(m, o) : m + o;
       }
     __syncthreads();
   }
@@ -469,11 +475,11 @@ __global__ void __launch_bounds__(256) k_diag(const double *__restrict__ U, cons
 
 __global__ void k_diag_final(const double *__restrict__ part, int nparts, double *__restrict__ out) {
   __shared__ double red[256 * kDiagVals];
-  double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nparts; b += blockDim.x)
     for (int c = 0; c < kDiagVals; ++c) {
       double o = part[b * kDiagVals + c];
-      acc[c] = (c == 7 || c == 8) ? fmax(acc[c], o) : acc[c] + o;
+      acc[c] = diag_is_max(c) ? fmax(acc[c], o) : acc[c] + o;
     }
   for (int c = 0; c < kDiagVals; ++c) red[threadIdx.x * kDiagVals + c] = acc[c];
   __syncthreads();
@@ -482,7 +488,7 @@ __global__ void k_diag_final(const double *__restrict__ part, int nparts, double
       for (int c = 0; c < kDiagVals; ++c) {
         double o = red[(threadIdx.x + w) * kDiagVals + c];
         double &m = red[threadIdx.x * kDiagVals + c];
-        m = (c == 7 || c == 8) ? fmax(m, o) : m + o;
+        m = diag_is_max(c) ? fmax(m, o) : m + o;
       }
     __syncthreads();
   }

@@ -17,7 +17,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
-           "sd_rk_step", "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_last_error",
+           "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_last_error",
            "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
            "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"]
 
@@ -62,7 +62,7 @@ class MlpShape(ctypes.Structure):
 class Diag(ctypes.Structure):
     _fields_ = [("ke", ctypes.c_double), ("enstrophy", ctypes.c_double), ("mass", ctypes.c_double),
                 ("mom", ctypes.c_double * 3), ("energy", ctypes.c_double), ("umax", ctypes.c_double),
-                ("nonfinite", ctypes.c_int)]
+                ("nonfinite", ctypes.c_int), ("smax", ctypes.c_double)]
 
 
 _lib = None
@@ -88,6 +88,7 @@ def load_library(path=LIB_PATH):
     L.sd_rhs.argtypes = [vp, vp, vp]
     L.sd_rk_step.argtypes = [vp, vp, ctypes.c_double]
     L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
+    L.sd_stable_dt.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.sd_timing.argtypes = [vp, ctypes.c_int]
     L.sd_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     sp = ctypes.POINTER(MlpShape)
@@ -108,7 +109,8 @@ def load_library(path=LIB_PATH):
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
-              "sd_diagnostics", "sd_timing", "sd_timing_read", "sd_mlp_round_weights", "sd_mlp_forward",
+              "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_mlp_round_weights",
+              "sd_mlp_forward",
               "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -202,7 +204,15 @@ class SD:
         if rc != SD_OK and not (rc == SD_ENONFINITE and not raise_nonfinite):
             _check(rc)
         return {"ke": d.ke, "enstrophy": d.enstrophy, "mass": d.mass, "mom": list(d.mom),
-                "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite)}
+                "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite), "smax": d.smax}
+
+    def stable_dt(self, u, cfl=0.3):
+        """cfl * min h / ((p + 1) max(|u| + c)) for the state u (sd_stable_dt)."""
+        self._check_state(u)
+        self._stream()
+        dt = ctypes.c_double()
+        _check(load_library().sd_stable_dt(self._ctx, ctypes.c_void_p(u.data_ptr()), cfl, ctypes.byref(dt)))
+        return dt.value
 
     def timing(self, enable=True):
         """Start (or stop) recording HIP events around every RHS evaluation."""

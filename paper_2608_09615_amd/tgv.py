@@ -5,8 +5,11 @@ another (the FP64 path is the reference of the FP32 and BF16x3 ones).
     python -m paper_2608_09615_amd.tgv --nel 32 --p 3 --t-end 20 --precisions fp64,fp32
 
 The state is the compressible TGV (Ma = 0.1, gamma = 1.4, Pr = 0.71) on the
-periodic box [0, 2 pi]^3; every run takes RK4 steps of equal size, dt_out / k
-with the smallest k that keeps dt below 0.3 h / ((p + 1)(1 + c0)).
+periodic box [0, 2 pi]^3; every run takes RK steps of equal size, dt_out / k
+with the smallest k that keeps dt below 0.3 h / ((p + 1)(1 + c0)).  With
+``--cfl`` the step adapts instead: each output interval takes the smallest k
+that keeps dt below the library's convective limit cfl h / ((p + 1) max(|u| + c))
+of the state at its start.
 """
 import json
 import math
@@ -25,7 +28,7 @@ def step_size(nel, p, dt_out, Ma=0.1, cfl=0.3):
 
 
 def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, dt_out=0.1, log=print,
-            integrator="rk4"):
+            integrator="rk4", cfl=None):
     """KE and enstrophy every dt_out up to t_end, and the wall time of the
     stepping (diagnostics included)."""
     import torch
@@ -39,9 +42,14 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
     t, ke, ens = [0.0], [d["ke"]], [d["enstrophy"]]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    steps = 0
     for i in range(1, nout + 1):
+        if cfl is not None:
+            k = max(1, math.ceil(dt_out / sd.stable_dt(u, cfl) - 1e-12))
+            dt = dt_out / k
         for _ in range(k):
             sd.rk_step(u, dt)
+        steps += k
         d = sd.diagnostics(u)
         if d["nonfinite"]:
             raise FloatingPointError(f"{precision} run turned non-finite before t={i * dt_out:.2f}")
@@ -55,7 +63,7 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
     wall = time.perf_counter() - t0
     sd.close()
     return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "integrator": integrator,
-            "dt": dt, "steps": nout * k,
+            "dt": dt, "cfl": cfl, "steps": steps,
             "t": t, "ke": ke, "enstrophy": ens, "wall_s": wall}
 
 
@@ -77,10 +85,11 @@ def main(argv=None):
     ap.add_argument("--dt-out", type=float, default=0.1)
     ap.add_argument("--precisions", default="fp64,fp32", help="the first one is the reference")
     ap.add_argument("--integrator", default="rk4", choices=["rk4", "ssprk54"])
+    ap.add_argument("--cfl", type=float, default=None, help="adaptive step with this Courant number")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
-    runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log, a.integrator)
+    runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log, a.integrator, a.cfl)
             for pr in a.precisions.split(",")]
     res = {"runs": runs, "errors": {r["precision"]: compare(r, runs[0]) for r in runs[1:]}}
     for r in runs[1:]:

@@ -210,14 +210,30 @@ def test_diagnostics_parity(torch_cuda, oracle_lib):
     prm = oracle_lib.make_params("ns")
     U = W.perturbed_tgv_state(nel, p, seed=9, noise=1e-3)
     from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd.sd import SDError
     sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
     d = sd.diagnostics(torch_cuda.from_numpy(U).to("cuda"))
     do = oracle_lib.diag_3d(U, nel, lo, hi, p, prm)
-    for k in ("ke", "enstrophy", "mass", "energy", "umax"):
+    for k in ("ke", "enstrophy", "mass", "energy", "umax", "smax"):
         assert abs(d[k] - do[k]) <= 1e-12 * abs(do[k]), k
     for i in range(3):
         assert abs(d["mom"][i] - do[f"mom{i}"]) <= 1e-12 * do["mass"]
     assert d["nonfinite"] is False
+    # the convective time step: cfl min h / ((p + 1) smax); the mesh is
+    # anisotropic in element count, so the smallest h is h_z = 2 pi / 5
+    u = torch_cuda.from_numpy(U).to("cuda")
+    for cfl in (0.3, 1.0):
+        dt = sd.stable_dt(u, cfl)
+        assert abs(dt - cfl * (2 * np.pi / 5) / ((p + 1) * do["smax"])) <= 1e-14 * dt
+    for cfl in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(SDError):
+            sd.stable_dt(u, cfl)
+    Ub = U.copy()
+    Ub[2, 4, 0, 1, 2] = 0.0                    # rho E = 0 with u != 0: P < 0
+    db = sd.diagnostics(torch_cuda.from_numpy(Ub).to("cuda"))
+    assert db["smax"] == float("inf") and db["nonfinite"] is False
+    with pytest.raises(SDError):
+        sd.stable_dt(torch_cuda.from_numpy(Ub).to("cuda"))
     U[5, 2, 1, 1, 1] = np.nan
     d = sd.diagnostics(torch_cuda.from_numpy(U).to("cuda"))
     assert d["nonfinite"] is True

@@ -95,5 +95,6 @@ def test_params_default_values(lib):
 def test_null_pointers(lib):
     assert lib.sd_rhs(None, None, None) == -1
     assert lib.sd_rk_step(None, None, 0.1) == -1
+    assert lib.sd_stable_dt(None, None, 0.3, None) == -1
     assert lib.sd_free(None) == 0
     assert lib.sd_state_size(None) == -1
