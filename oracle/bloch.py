@@ -1,4 +1,5 @@
-"""Temporal (Bloch) eigenanalysis of the 1-D SD diffusion operator, section 3.
+"""Temporal (Bloch) eigenanalysis of the 1-D SD diffusion operator, section 3,
+and the combined-mode analysis of the appendix.
 
 Test infrastructure only.  The matrices follow the section's derivation:
 the continuous solution operator H(theta), the one-sided gradient operators
@@ -58,5 +59,8 @@ def combined_mode(p, theta, t, J=1.0, scheme="compact", eta_ip=0.0, h=2.0):
     gam = np.linalg.solve(N, u0)
     ut = N @ (gam * np.exp(lam * t))
     G = np.vdot(u0, ut) / np.vdot(u0, u0)
-    omega = -1j / t * np.log(G)
+    # u(t) = sum_j gamma_j mu_j exp(-i omega_j t) makes G = exp(-i omega t)
+    # for a single mode, so omega = (i / t) log G (printed with the other
+    # sign; this one reduces to omega = i lambda when u0 is an eigenvector)
+    omega = 1j / t * np.log(G)
     return G, omega
