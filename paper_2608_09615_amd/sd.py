@@ -19,7 +19,8 @@ INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
            "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_last_error",
            "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
-           "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"]
+           "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
+           "sd_bloch"]
 
 
 class SDError(RuntimeError):
@@ -65,6 +66,10 @@ class Diag(ctypes.Structure):
                 ("nonfinite", ctypes.c_int), ("smax", ctypes.c_double)]
 
 
+class BlochCfg(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("scheme", ctypes.c_int), ("J", ctypes.c_double), ("eta_ip", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -106,12 +111,14 @@ def load_library(path=LIB_PATH):
     L.sd_closure_set.argtypes = [vp, sp, vp, vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                  ctypes.POINTER(ctypes.c_float), ctypes.c_float]
     L.sd_closure_rejected.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    L.sd_bloch.argtypes = [ctypes.POINTER(BlochCfg), vp, ctypes.c_longlong, vp, ctypes.c_int, vp, vp, vp, vp, vp]
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
               "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_mlp_round_weights",
               "sd_mlp_forward",
-              "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected"):
+              "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
+              "sd_bloch"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -340,4 +347,35 @@ def filter_state(fine, nel_fine, ratio, p, nv):
     out = torch.empty((nec, nv) + (p + 1,) * 3, dtype=torch.float64, device="cuda")
     nel = (ctypes.c_int * 3)(*nel_fine)
     _check(load_library().sd_filter(_ptr(fine), nel, ratio, p, nv, _ptr(out), _stream()))
+    return out
+
+
+def bloch(p, scheme, theta, t=None, J=0.5, eta_ip=0.0, matrices=True, eigs=True):
+    """Batched Bloch analysis of the 1-D diffusion operator (sd_bloch).
+
+    theta: CUDA float64 tensor of wavenumbers per element; t: CUDA float64
+    tensor of times for the combined mode (None: skip).  Returns complex128
+    tensors "B" [ntheta, p+1, p+1], "lam" [ntheta, p+1] and, with t, "G" and
+    "omega" [ntheta, nt]."""
+    import torch
+    if theta.dtype != torch.float64 or not theta.is_cuda or not theta.is_contiguous():
+        raise ValueError("theta must be a contiguous CUDA float64 tensor")
+    if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+        raise ValueError("t must be a contiguous CUDA float64 tensor")
+    n, nth = p + 1, theta.numel()
+    nt = 0 if t is None else t.numel()
+    dev = theta.device
+    out = {}
+    B = torch.empty((nth, n, n, 2), dtype=torch.float64, device=dev) if matrices else None
+    lam = torch.empty((nth, n, 2), dtype=torch.float64, device=dev) if eigs else None
+    G = torch.empty((nth, nt, 2), dtype=torch.float64, device=dev) if nt else None
+    om = torch.empty((nth, nt, 2), dtype=torch.float64, device=dev) if nt else None
+    cfg = BlochCfg(p, SCHEMES[scheme], J, eta_ip)
+    ptr = lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(load_library().sd_bloch(ctypes.byref(cfg), ptr(theta), nth, ptr(t), nt, ptr(B), ptr(lam), ptr(G),
+                                   ptr(om), stream))
+    for k, x in (("B", B), ("lam", lam), ("G", G), ("omega", om)):
+        if x is not None:
+            out[k] = torch.view_as_complex(x)
     return out

@@ -96,5 +96,28 @@ def test_null_pointers(lib):
     assert lib.sd_rhs(None, None, None) == -1
     assert lib.sd_rk_step(None, None, 0.1) == -1
     assert lib.sd_stable_dt(None, None, 0.3, None) == -1
+
+
+@pytest.mark.parametrize("cfg,ntheta,rc", [
+    (None, 1, -1),
+    (dict(p=0), 1, -5), (dict(p=9), 1, -5), (dict(scheme=4), 1, -1),
+    (dict(J=0.0), 1, -1), (dict(J=float("inf")), 1, -1), (dict(eta_ip=-0.1), 1, -1),
+    (dict(eta_ip=float("nan")), 1, -1), (dict(), -1, -1), (dict(), 3, -1),
+])
+def test_bloch_argument_checks(lib, cfg, ntheta, rc):
+    """Rejected before any device work (theta is NULL here)."""
+    from paper_2608_09615_amd import sd
+    c = None
+    if cfg is not None:
+        kw = dict(p=3, scheme=1, J=0.5, eta_ip=0.0)
+        kw.update(cfg)
+        c = ctypes.byref(sd.BlochCfg(kw["p"], kw["scheme"], kw["J"], kw["eta_ip"]))
+    assert lib.sd_bloch(c, None, ntheta, None, 0, None, None, None, None, None) == rc
+
+
+def test_bloch_nothing_to_do(lib):
+    from paper_2608_09615_amd import sd
+    c = sd.BlochCfg(3, 1, 0.5, 0.0)
+    assert lib.sd_bloch(ctypes.byref(c), None, 0, None, 0, None, None, None, None, None) == 0
     assert lib.sd_free(None) == 0
     assert lib.sd_state_size(None) == -1
