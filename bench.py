@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (calibrates byte counters)")
     ap.add_argument("--precisions", default="fp32,fp64", help="fp32 and fp64 always for the JSON line; bf16x3 optional")
+    ap.add_argument("--bloch-theta", type=int, default=1 << 16,
+                    help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
+    ap.add_argument("--bloch-only", action="store_true", help="time only the Bloch sweep and print its record")
     return ap.parse_args()
 
 
@@ -164,6 +167,62 @@ def cpu_baseline(W, args, U0):
                       f"({sec:.1f} s wall, OpenMP over elements)"}
 
 
+BLOCH_TIMES = (0.01, 0.1, 1.0)
+BLOCH_TAYLOR_DEGREE = 18
+
+
+def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
+    """Batched Bloch analysis (section 3, appendix): 2^16 wavenumbers in
+    [0, pi], unit elements.  Times (a) B(theta) and its eigenvalues, (b) B and
+    the combined mode at three times, (c) everything, with HIP events on the
+    stream the kernel runs on.  Roofline of (b): every complex multiply-add is
+    8 FP64 flops; per (theta, t) the Taylor polynomial and the squarings cost
+    (18 + s) (p+1)^3 of them, s being the squarings the kernel takes
+    (||B t||_1 / 2^s <= 1/2, recomputed here from the returned B), and
+    building B about 2 (p+1)^3; the eigenvalue iteration is not counted."""
+    import numpy as np
+    from paper_2608_09615_amd.sd import bloch
+    n = p + 1
+    th = torch.linspace(0.0, math.pi, args.bloch_theta, dtype=torch.float64, device="cuda")
+    t = torch.tensor(BLOCH_TIMES, dtype=torch.float64, device="cuda")
+    B = bloch(p, scheme, th, None, eigs=False)["B"]
+    norm1 = B.abs().sum(dim=1).max(dim=1).values.cpu().numpy()
+    cmacs = 0.0
+    for tv in BLOCH_TIMES:
+        x = norm1 * tv
+        sq = np.zeros_like(x)
+        while np.any(x > 0.5):
+            big = x > 0.5
+            x[big] *= 0.5
+            sq[big] += 1
+        cmacs += float(np.sum(BLOCH_TAYLOR_DEGREE + sq)) * n ** 3
+    cmacs += 2.0 * n ** 3 * args.bloch_theta
+    stream = torch.cuda.current_stream()
+
+    def timed(**kw):
+        bloch(p, scheme, th, **kw)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            bloch(p, scheme, th, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_eig = timed(t=None, matrices=False, eigs=True)
+    ms_cm = timed(t=t, matrices=False, eigs=False)
+    ms_all = timed(t=t, matrices=True, eigs=True)
+    achieved = 8.0 * cmacs / (ms_cm * 1e-3) / 1e12
+    return {"config": f"p={p} {scheme}, {args.bloch_theta} wavenumbers in [0, pi], J = 1/2, "
+                      f"t = {', '.join(str(x) for x in BLOCH_TIMES)}",
+            "mtheta_per_s": {"eigenvalues": args.bloch_theta / ms_eig / 1e3,
+                             "combined_mode": args.bloch_theta / ms_cm / 1e3,
+                             "all": args.bloch_theta / ms_all / 1e3},
+            "ms": {"eigenvalues": ms_eig, "combined_mode": ms_cm, "all": ms_all},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernels": "k_bloch (combined mode)"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -175,6 +234,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.bloch_only:
+        print(json.dumps({"bloch": bloch_bench(torch, args)}), flush=True)
+        return
     nel = (args.nel,) * 3
     U0 = W.tgv_state(nel, args.p)
     h = 2 * math.pi / args.nel
@@ -246,6 +308,8 @@ def main():
     if rbf:
         rec["bf16x3"] = {"value": rbf["gdofs"], "ms_per_step": rbf["ms_per_step"], "dtype": "f32+bf16x3",
                          "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "bf16x3")}
+    if args.bloch_theta > 0:
+        rec["bloch"] = bloch_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0)
     print(json.dumps(rec), flush=True)
