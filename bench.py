@@ -64,24 +64,35 @@ def parse():
     return ap.parse_args()
 
 
+# the sources that define k_traces_ns and k_rhs_ns, their operators and their
+# launch configuration, with the compiler flags (any change there invalidates
+# the counter record)
+TRAFFIC_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispatch.inc", "sd_operators.cpp"]
+
+
+def sources_sha256():
+    import hashlib
+    from paper_2608_09615_amd.build import HIPCC_FLAGS
+    h = hashlib.sha256()
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2608_09615_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(args, precision):
     """HBM bytes per RK stage (k_traces_ns + k_rhs_ns) from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, or None when the workload differs or
     a kernel source has changed since the counters were taken."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", "rhs_traffic_tgv32p3.json")
     if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip
             and args.integrator == "rk4" and os.path.exists(path)):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for src in sorted(glob.glob(os.path.join(ROOT, "paper_2608_09615_amd", "csrc", "*"))):
-        h.update(os.path.basename(src).encode())
-        with open(src, "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    if sources_sha256() != rec["sources_sha256"]:
         return None
     return rec["per_stage_bytes"].get(precision)
 
