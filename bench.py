@@ -231,7 +231,8 @@ def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
                              "all": args.bloch_theta / ms_all / 1e3},
             "ms": {"eigenvalues": ms_eig, "combined_mode": ms_cm, "all": ms_all},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernels": "k_bloch (combined mode)"}}
+                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                         "kernels": "k_bloch_lane_cm (combined mode)"}}
 
 
 def main():

@@ -10,10 +10,12 @@
 // the optional interior penalty, fluxes and divergence), every neighbour
 // quantity being z^{+-1} times the element's own.
 //
-// One block of 64 lanes (one wavefront) handles one theta at a time: the
-// matrices live in LDS, lanes run over matrix entries, and every branch
+// n >= 5: one block of 64 lanes (one wavefront) handles one theta at a time:
+// the matrices live in LDS, lanes run over matrix entries, and every branch
 // depends only on LDS values that all lanes read alike, so the block's
-// barriers are reached uniformly.
+// barriers are reached uniformly.  n <= 4: one lane per theta (B and its
+// eigenvalues) or per (theta, t) pair (combined mode) with the matrices in
+// registers (k_bloch_lane_eig, k_bloch_lane_cm, at the end of this file).
 #pragma once
 
 namespace sd {
@@ -29,6 +31,10 @@ __device__ __forceinline__ cplx operator*(cplx a, cplx b) {
 }
 __device__ __forceinline__ cplx operator*(double s, cplx a) { return cplx{s * a.re, s * a.im}; }
 __device__ __forceinline__ cplx conjg(cplx a) { return cplx{a.re, -a.im}; }
+// acc + a b as four fused multiply-adds
+__device__ __forceinline__ cplx cfma(cplx a, cplx b, cplx acc) {
+  return cplx{fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
 __device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
 __device__ __forceinline__ double cabs(cplx a) { return hypot(a.re, a.im); }
 __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
@@ -84,7 +90,7 @@ struct BlochSmem {
 
 // Column c of B(theta) (lane c < N).
 template <int N>
-__device__ void bloch_column(const BlochOps<N> &o, cplx z, int c, cplx *A) {
+__device__ __forceinline__ void bloch_column(const BlochOps<N> &o, cplx z, int c, cplx *A) {
   const cplx zi = conjg(z);
   const double T0 = o.Lend[0][c], T1 = o.Lend[1][c];
   // common solution at the left face (left neighbour's right trace z^-1 T1)
@@ -325,7 +331,7 @@ __device__ __forceinline__ void cmatmul(const cplx *P, const cplx *Q, cplx *C, i
     if (e < N * N) {
       int i = e / N, j = e % N;
 #pragma unroll
-      for (int k = 0; k < N; ++k) acc = acc + P[i * N + k] * Q[k * N + j];
+      for (int k = 0; k < N; ++k) acc = cfma(P[i * N + k], Q[k * N + j], acc);
     }
     out[r] = acc;
   }
@@ -441,6 +447,295 @@ __global__ void __launch_bounds__(64) k_bloch(BlochOps<N> o, const double *__res
         }
       }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small degrees (n <= 4): one lane per theta, every matrix in registers and
+// every loop over matrix indices unrolled.  Same arithmetic as above; the QR
+// iteration runs on the whole matrix instead of the active window: every
+// negligible subdiagonal is set to zero, which makes the rotations across it
+// identities, so each diagonal block undergoes its own shifted QR step (the
+// shift is taken from the trailing undeflated block).
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ cplx pick(const cplx (&a)[N * N], int i, int j) {
+  cplx r = cx(0.0);
+#pragma unroll
+  for (int e = 0; e < N * N; ++e)
+    if (e == i * N + j) r = a[e];
+  return r;
+}
+
+template <int N>
+__device__ void lane_eigs(const cplx (&A)[N * N], cplx (&lam)[N]) {
+  cplx H[N * N];
+#pragma unroll
+  for (int e = 0; e < N * N; ++e) H[e] = A[e];
+  // Householder reduction to Hessenberg form
+#pragma unroll
+  for (int k = 0; k + 2 < N; ++k) {
+    double nx = 0.0, tail = 0.0;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) nx += cabs2(H[i * N + k]);
+#pragma unroll
+    for (int i = k + 2; i < N; ++i) tail += cabs2(H[i * N + k]);
+    if (tail > 0.0) {
+      nx = sqrt(nx);
+      cplx v[N];
+      const cplx x0 = H[(k + 1) * N + k];
+      const double a0 = cabs(x0);
+      const cplx ph = a0 > 0.0 ? cplx{x0.re / a0, x0.im / a0} : cx(1.0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = cx(0.0);
+      v[k + 1] = x0 + nx * ph;
+#pragma unroll
+      for (int i = k + 2; i < N; ++i) v[i] = H[i * N + k];
+      double nv = 0.0;
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) nv += cabs2(v[i]);
+      nv = 1.0 / sqrt(nv);
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) v[i] = nv * v[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        cplx w = cx(0.0);
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) w = w + conjg(v[i]) * H[i * N + j];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) H[i * N + j] = H[i * N + j] - 2.0 * (v[i] * w);
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        cplx w = cx(0.0);
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) w = w + H[i * N + j] * v[j];
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) H[i * N + j] = H[i * N + j] - 2.0 * (w * conjg(v[j]));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j + 1 < i; ++j) H[i * N + j] = cx(0.0);
+  const double eps = 2.220446049250313e-16;
+  int hi = N - 1, iters = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) lam[i] = cx(__builtin_nan(""), __builtin_nan(""));
+  for (int guard = 0; guard < N * (60 * N + 1) && hi >= 0; ++guard) {
+    // zero every negligible subdiagonal
+#pragma unroll
+    for (int l = 1; l < N; ++l) {
+      const double d = cabs(H[(l - 1) * N + l - 1]) + cabs(H[l * N + l]);
+      if (cabs(H[l * N + l - 1]) <= eps * d) H[l * N + l - 1] = cx(0.0);
+    }
+    const cplx sub = hi > 0 ? pick<N>(H, hi, hi - 1) : cx(0.0);
+    if (sub.re == 0.0 && sub.im == 0.0) {
+      const cplx ev = pick<N>(H, hi, hi);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (i == hi) lam[i] = ev;
+      --hi;
+      iters = 0;
+      continue;
+    }
+    if (iters >= 60 * N) break;
+    cplx mu;
+    {
+      const cplx a = pick<N>(H, hi - 1, hi - 1), b = pick<N>(H, hi - 1, hi), c = sub, d = pick<N>(H, hi, hi);
+      if (iters % 10 == 9) {
+        mu = d + cx(0.75 * cabs(c), 0.0);
+      } else {
+        const cplx tr2 = 0.5 * (a + d);
+        const cplx disc = csqrt_(0.25 * ((a - d) * (a - d)) + b * c);
+        const cplx m1 = tr2 + disc, m2 = tr2 - disc;
+        mu = cabs2(m1 - d) <= cabs2(m2 - d) ? m1 : m2;
+      }
+    }
+    ++iters;
+#pragma unroll
+    for (int i = 0; i < N; ++i) H[i * N + i] = H[i * N + i] - mu;
+    double rc[N];
+    cplx rs[N];
+#pragma unroll
+    for (int k = 0; k + 1 < N; ++k) {
+      const cplx x = H[k * N + k], y = H[(k + 1) * N + k];
+      const double r = sqrt(cabs2(x) + cabs2(y));
+      double cc = 1.0;
+      cplx sn = cx(0.0);
+      if (r != 0.0) {
+        const double ax = cabs(x);
+        if (ax == 0.0) {
+          cc = 0.0;
+          sn = cdiv(conjg(y), cx(cabs(y)));
+        } else {
+          cc = ax / r;
+          sn = (1.0 / r) * (cplx{x.re / ax, x.im / ax} * conjg(y));
+        }
+      }
+      rc[k] = cc;
+      rs[k] = sn;
+#pragma unroll
+      for (int j = k; j < N; ++j) {
+        const cplx xj = H[k * N + j], yj = H[(k + 1) * N + j];
+        H[k * N + j] = cc * xj + sn * yj;
+        H[(k + 1) * N + j] = cc * yj - conjg(sn) * xj;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k + 1 < N; ++k) {
+#pragma unroll
+      for (int i = 0; i <= (k + 1 < N - 1 ? k + 1 : N - 1); ++i) {
+        const cplx xi = H[i * N + k], yi = H[i * N + k + 1];
+        H[i * N + k] = rc[k] * xi + conjg(rs[k]) * yi;
+        H[i * N + k + 1] = rc[k] * yi - rs[k] * xi;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) H[i * N + i] = H[i * N + i] + mu;
+  }
+  // real part descending, then imaginary part (a sorting network)
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j + 1 < N - i; ++j) {
+      const cplx a = lam[j], b = lam[j + 1];
+      if (a.re < b.re || (a.re == b.re && a.im > b.im)) {
+        lam[j] = b;
+        lam[j + 1] = a;
+      }
+    }
+}
+
+// B is built here (about 2 n^3 operations), so that only two matrices
+// occupy registers.
+template <int N>
+__device__ void lane_combined(const BlochOps<N> &o, cplx z, const cplx (&u0)[N], double t, cplx &G, cplx &om) {
+  cplx X[N * N], Y[N * N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) bloch_column<N>(o, z, c, X);
+  double nrm = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double cs = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) cs += cabs(X[i * N + j]);
+    nrm = fmax(nrm, cs);
+  }
+  nrm *= t;
+  int sq = 0;
+  while (nrm > 0.5 && sq < 1000) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double sc = ldexp(t, -sq);
+#pragma unroll
+  for (int e = 0; e < N * N; ++e) {
+    X[e] = sc * X[e];
+    Y[e] = cx(e / N == e % N ? 1.0 : 0.0);
+  }
+  // Horner, one column at a time: column j of X Y needs only column j of Y
+  for (int m = 18; m >= 1; --m) {
+    const double inv = 1.0 / m;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      cplx col[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        cplx acc = cx(0.0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc = cfma(X[i * N + k], Y[k * N + j], acc);
+        col[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) Y[i * N + j] = cplx{fma(inv, col[i].re, i == j ? 1.0 : 0.0), inv * col[i].im};
+    }
+  }
+  for (int q = 0; q < sq; ++q) {
+#pragma unroll
+    for (int e = 0; e < N * N; ++e) {
+      const int i = e / N, j = e % N;
+      cplx acc = cx(0.0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc = cfma(Y[i * N + k], Y[k * N + j], acc);
+      X[e] = acc;
+    }
+#pragma unroll
+    for (int e = 0; e < N * N; ++e) Y[e] = X[e];
+  }
+  cplx num = cx(0.0);
+  double den = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    cplx ui = cx(0.0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) ui = ui + Y[i * N + j] * u0[j];
+    num = num + conjg(u0[i]) * ui;
+    den += cabs2(u0[i]);
+  }
+  G = (1.0 / den) * num;
+  om = cplx{-atan2(G.im, G.re) / t, log(cabs(G)) / t};
+}
+
+// B(theta) and its eigenvalues, one lane per theta
+template <int N>
+__global__ void __launch_bounds__(256) k_bloch_lane_eig(BlochOps<N> o, const double *__restrict__ theta,
+                                                        long long ntheta, double *__restrict__ Bout,
+                                                        double *__restrict__ lam_out) {
+  const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= ntheta) return;
+  const double th = theta[it];
+  const cplx z = cplx{cos(th), sin(th)};
+  cplx A[N * N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) bloch_column<N>(o, z, c, A);
+  if (Bout)
+#pragma unroll
+    for (int e = 0; e < N * N; ++e) {
+      Bout[(it * N * N + e) * 2] = A[e].re;
+      Bout[(it * N * N + e) * 2 + 1] = A[e].im;
+    }
+  if (lam_out) {
+    cplx lam[N];
+    lane_eigs<N>(A, lam);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      lam_out[(it * N + i) * 2] = lam[i].re;
+      lam_out[(it * N + i) * 2 + 1] = lam[i].im;
+    }
+  }
+}
+
+// combined mode, one lane per (theta, t) pair (t fastest)
+template <int N>
+__global__ void __launch_bounds__(256) k_bloch_lane_cm(BlochOps<N> o, const double *__restrict__ theta,
+                                                       long long ntheta, const double *__restrict__ tv, int nt,
+                                                       double *__restrict__ Gout, double *__restrict__ om_out) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ntheta * nt) return;
+  const long long it = id / nt;
+  const int k = (int)(id % nt);
+  const double th = theta[it], t = tv[k];
+  cplx G = cx(__builtin_nan(""), __builtin_nan("")), om = G;
+  if (t > 0.0 && isfinite(t)) {
+    const cplx z = cplx{cos(th), sin(th)};
+    cplx u0[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double ph = 0.5 * th * (o.xs[c] + 1.0);
+      u0[c] = cplx{cos(ph), sin(ph)};
+    }
+    lane_combined<N>(o, z, u0, t, G, om);
+  }
+  if (Gout) {
+    Gout[id * 2] = G.re;
+    Gout[id * 2 + 1] = G.im;
+  }
+  if (om_out) {
+    om_out[id * 2] = om.re;
+    om_out[id * 2 + 1] = om.im;
   }
 }
 
