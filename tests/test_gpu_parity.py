@@ -271,6 +271,36 @@ def test_tgv_32cubed_sampled_parity(torch_cuda, oracle_lib):
             assert err < tol, (scheme, precision, err, sens)
 
 
+@pytest.mark.parametrize("nel1,p", [(64, 3), (43, 5)])
+def test_tgv_re5000_full_size_sampled_parity(torch_cuda, oracle_lib, nel1, p):
+    """Full sizes of the Re = 5000 TGV workloads (64^3 elements at p = 3 and
+    43^3 at p = 5, about 17 M and 21 M solution points), both schemes and the
+    three precisions, in the launch configuration the benchmark times:
+    sampled elements (corners of the box included) against the oracle's
+    element-wise RHS.  The state is the phase-shifted TGV with pointwise noise
+    (a solenoidal perturbation at this size would dominate the test's time).
+    FP64 bar: max(1e-12, 4 x the one-ulp sensitivity measured here)."""
+    nel = (nel1,) * 3
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns", Re=5000.0)
+    print(f"[re5000] {nel1}^3 p={p}: building the state", flush=True)
+    U = W.perturbed_tgv_state(nel, p, seed=33, noise=1e-3, amp=0.0)
+    ne = nel1 ** 3
+    rng = np.random.Generator(np.random.PCG64(6))
+    sel = np.unique(np.concatenate([rng.integers(0, ne, 40), [0, nel1 - 1, nel1 ** 2 - 1, ne - 1]]))
+    for scheme in ("compact", "br1"):
+        Ro, sens = ulp_sensitivity(oracle_lib, U, nel, lo, hi, p, scheme, prm, sel)
+        assert sens < 1e-10
+        for precision, tol in (("fp64", max(FP64_TOL, 4 * sens)), ("fp32", FP32_TOL_NS),
+                               ("bf16x3", BF16X3_TOL_NS)):
+            R, sd = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", precision, lo, hi, Re=5000.0)
+            sd.close()
+            err = relerr(R[sel], Ro)
+            print(f"{nel1}^3 p={p} {scheme} {precision}: error {err:.3e} (ulp sensitivity {sens:.3e})", flush=True)
+            assert err < tol, (scheme, precision, err, sens)
+            del R
+
+
 # ---------------------------------------------------------------------------
 # Interior-penalty variant (section 3): the normal component of the common
 # gradient gains tau (u_R - u_L), tau = eta_IP (p+1)^2 / h.
