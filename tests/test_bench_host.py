@@ -1,0 +1,28 @@
+"""Host logic of bench.py (CPU only): the one-GPU guard and the use of the
+committed HBM-traffic record."""
+import argparse
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, cwd=ROOT, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
+
+
+def test_traffic_record_applies_to_its_workload_only():
+    sys.path.insert(0, ROOT)
+    import bench
+    base = dict(nel=32, p=3, scheme="compact", eta_ip=0.0, integrator="rk4")
+    rec_ok = bench.measured_traffic(argparse.Namespace(**base), "fp32")
+    # the committed record was taken on the current kernel sources (this fails
+    # after a change to them until the counters are taken again)
+    assert rec_ok is not None and 1.68e8 < rec_ok < 2e9
+    for change in (dict(nel=64), dict(p=5), dict(scheme="br1"), dict(eta_ip=0.1), dict(integrator="ssprk54")):
+        args = argparse.Namespace(**{**base, **change})
+        assert bench.measured_traffic(args, "fp32") is None, change
