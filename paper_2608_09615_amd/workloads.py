@@ -184,3 +184,54 @@ def random_scalar_3d(nel, p, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     ne = nel[0] * nel[1] * nel[2]
     return rng.uniform(-1, 1, (ne, 1, p + 1, p + 1, p + 1))
+
+
+# ---------------------------------------------------------------------------
+# Hexahedral meshes given by node coordinates (curvilinear elements).
+
+def mesh_nodes(nel, lo, hi, q=1, displacement=None, rotation=None):
+    """Node coordinates Xg[e][c][b][a][3] of a structured nel[0] x nel[1] x
+    nel[2] mesh of the box [lo, hi]: q + 1 equispaced nodes per direction
+    and element (ends included, a along x fastest), moved by
+    displacement(X, Y, Z) -> (dx, dy, dz) and then by the rotation matrix."""
+    t = np.linspace(0.0, 1.0, q + 1)
+    axes = []
+    for d in range(3):
+        h = (hi[d] - lo[d]) / nel[d]
+        axes.append(lo[d] + h * (np.arange(nel[d])[:, None] + t[None, :]))   # [N_d, q+1]
+    X = axes[0][None, None, :, None, None, :]
+    Y = axes[1][None, :, None, None, :, None]
+    Z = axes[2][:, None, None, :, None, None]
+    shape = (nel[2], nel[1], nel[0], q + 1, q + 1, q + 1)
+    X, Y, Z = np.broadcast_to(X, shape), np.broadcast_to(Y, shape), np.broadcast_to(Z, shape)
+    P = np.stack([X, Y, Z], axis=-1).astype(np.float64)
+    if displacement is not None:
+        P = P + np.stack(displacement(X, Y, Z), axis=-1)
+    if rotation is not None:
+        P = P @ np.asarray(rotation, dtype=np.float64).T
+    # [ez, ey, ex, c, b, a, 3] -> [e, c, b, a, 3]
+    return np.ascontiguousarray(P.reshape(-1, q + 1, q + 1, q + 1, 3))
+
+
+def periodic_wave_displacement(eps, L=2 * math.pi):
+    """A smooth displacement of period L in every coordinate."""
+    k = 2 * math.pi / L
+
+    def disp(X, Y, Z):
+        return (eps * np.sin(k * Y) * np.sin(k * Z), eps * np.sin(k * Z) * np.sin(k * X),
+                eps * np.sin(k * X) * np.sin(k * Y))
+    return disp
+
+
+def map_points(Xg, p):
+    """Physical coordinates [e][k][j][i][3] of the solution points of the
+    mesh Xg (tensor Lagrange interpolation of the equispaced nodes)."""
+    q = Xg.shape[1] - 1
+    nodes = np.linspace(-1.0, 1.0, q + 1)
+    xs, _ = gl_nodes(p + 1)
+    V = np.ones((len(xs), q + 1))
+    for a in range(q + 1):
+        for b in range(q + 1):
+            if b != a:
+                V[:, a] *= (xs - nodes[b]) / (nodes[a] - nodes[b])
+    return np.einsum("ecbav,ia,jb,kc->ekjiv", Xg, V, V, V)
