@@ -160,6 +160,23 @@ int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
  * positive signal speed; SD_EUNSUPPORTED for scalar physics. */
 int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
 
+/* Curvilinear hexahedra (section 2.3: q = J u, G = S.F, H = S^T u with
+ * S = adj(dx/dxi)) for a 3-D diffusion context in FP64.  nodes: HOST array
+ * [ne][q+1][q+1][q+1][3] (copied), the coordinates of q + 1 equispaced
+ * nodes per direction of every element (ends included, the first index
+ * along zeta, the last along xi), q = 1 or 2; element e keeps its place in
+ * the structured periodic connectivity of the mesh given to sd_init (the
+ * box lo/hi is no longer used), and shared faces must carry the same nodes.
+ * The library evaluates S at the flux points and 1/det J at the solution
+ * points, stores them on the device (about 9(p+2)(p+1)^2 + (p+1)^3 doubles
+ * per element) and from then on sd_rhs and sd_rk_step use them.  Constants
+ * are preserved exactly when 2q <= p + 1.  Returns SD_EINVAL for a null
+ * argument, q outside {1, 2} or an element whose det J is not positive at
+ * a solution point; SD_EUNSUPPORTED for other physics, dimensions or
+ * precisions, or with the interior penalty on; SD_ENOMEM / SD_EHIP on
+ * device failures.  Calling it again replaces the geometry. */
+int sd_set_geometry(sd_ctx *ctx, const double *nodes, int q);
+
 /* Timing of the right-hand side kernels: with enable = 1 every later RHS
  * evaluation of the context (sd_rhs and the four inside sd_rk_step) is
  * bracketed by a pair of HIP events on the context's stream (up to 4096

@@ -501,6 +501,8 @@ __global__ void k_diag_final(const double *__restrict__ part, int nparts, double
 #include "sd_ns_kernel.h"
 #include "sd_mlp.h"
 #include "sd_bloch_kernel.h"
+#include "sd_curv_kernel.h"
 #include "sd_dispatch.inc"
 #include "sd_closure.inc"
 #include "sd_bloch.inc"
+#include "sd_curv.inc"

@@ -17,7 +17,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
-           "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_last_error",
+           "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
+           "sd_last_error",
            "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
            "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
            "sd_bloch"]
@@ -94,6 +95,7 @@ def load_library(path=LIB_PATH):
     L.sd_rk_step.argtypes = [vp, vp, ctypes.c_double]
     L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
     L.sd_stable_dt.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    L.sd_set_geometry.argtypes = [vp, vp, ctypes.c_int]
     L.sd_timing.argtypes = [vp, ctypes.c_int]
     L.sd_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     sp = ctypes.POINTER(MlpShape)
@@ -115,7 +117,8 @@ def load_library(path=LIB_PATH):
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
-              "sd_diagnostics", "sd_stable_dt", "sd_timing", "sd_timing_read", "sd_mlp_round_weights",
+              "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
+              "sd_mlp_round_weights",
               "sd_mlp_forward",
               "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
               "sd_bloch"):
@@ -212,6 +215,16 @@ class SD:
             _check(rc)
         return {"ke": d.ke, "enstrophy": d.enstrophy, "mass": d.mass, "mom": list(d.mom),
                 "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite), "smax": d.smax}
+
+    def set_geometry(self, nodes):
+        """Curvilinear elements (3-D diffusion, FP64): nodes[e][c][b][a][3],
+        q + 1 equispaced nodes per direction of every element (q = 1 or 2)."""
+        import numpy as np
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        q = nodes.shape[1] - 1
+        if nodes.ndim != 5 or nodes.shape[1:] != (q + 1, q + 1, q + 1, 3) or nodes.shape[0] != self.ne:
+            raise ValueError(f"nodes must have shape [{self.ne}, q+1, q+1, q+1, 3]")
+        _check(load_library().sd_set_geometry(self._ctx, nodes.ctypes.data_as(ctypes.c_void_p), q))
 
     def stable_dt(self, u, cfl=0.3):
         """cfl * min h / ((p + 1) max(|u| + c)) for the state u (sd_stable_dt)."""

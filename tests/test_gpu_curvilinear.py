@@ -1,0 +1,133 @@
+"""Curvilinear hexahedra on the GPU (3-D diffusion, FP64) against the
+curvilinear reference: right-hand sides on affine, rotated (full S) and
+curved meshes, ragged element counts, p = 1..6, both schemes; RK4 and
+SSP-RK(5,4) steps; argument checks.  Bar: 1e-12 of max|R| (the metric terms
+are computed independently on both sides, each to a few ulps)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import curvilinear as C
+from oracle import ssprk
+from paper_2608_09615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+BOX = ((0.0, 0.0, 0.0), (2 * math.pi,) * 3)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(torch, nel, p, scheme, Xg, nu=0.7, **kw):
+    from paper_2608_09615_amd import SD
+    print(f"[curv] nel={nel} p={p} {scheme} q={Xg.shape[1] - 1}", flush=True)
+    sd = SD(nel, p, scheme=scheme, physics="diffusion", precision="fp64", lo=[0.0] * 3, hi=[1.0] * 3, nu=nu, **kw)
+    sd.set_geometry(Xg)
+    return sd
+
+
+def meshes(nel):
+    Q = np.array([[0.6, -0.8, 0.0], [0.48, 0.36, -0.8], [0.64, 0.48, 0.6]])
+    return {
+        "affine": W.mesh_nodes(nel, (0.0, 0.0, 0.0), (1.0, 2.0, 1.5), q=1),
+        "rotated": W.mesh_nodes(nel, (0.0, 0.0, 0.0), (1.0, 2.0, 1.5), q=1, rotation=Q),
+        "curved": W.mesh_nodes(nel, *BOX, q=2, displacement=W.periodic_wave_displacement(0.2)),
+    }
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_curvilinear_rhs_parity(torch_cuda, scheme, p):
+    for nel in ((3, 2, 4), (1, 3, 2)):
+        E, n = int(np.prod(nel)), p + 1
+        u = np.random.Generator(np.random.PCG64(10 * p + E)).normal(size=(E, n, n, n))
+        for name, Xg in meshes(nel).items():
+            sd = make(torch_cuda, nel, p, scheme, Xg)
+            R = sd.rhs(torch_cuda.from_numpy(u[:, None]).to("cuda")).cpu().numpy()[:, 0]
+            sd.close()
+            Ro = C.rhs(u, nel, Xg, p, scheme, nu=0.7)
+            err = np.abs(R - Ro).max() / np.abs(Ro).max()
+            print(f"  {name} {nel}: {err:.2e}")
+            assert err < 1e-12, (name, nel, err)
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_curvilinear_16cubed(torch_cuda, scheme):
+    """16^3 degree-2 elements at p = 3 (262 144 solution points), every value."""
+    nel, p = (16, 16, 16), 3
+    Xg = W.mesh_nodes(nel, *BOX, q=2, displacement=W.periodic_wave_displacement(0.3))
+    x = W.map_points(Xg, p)
+    u = np.sin(x[..., 0]) * np.cos(2 * x[..., 1]) * np.sin(x[..., 2]) + 0.01 * np.random.Generator(
+        np.random.PCG64(4)).normal(size=x.shape[:-1])
+    sd = make(torch_cuda, nel, p, scheme, Xg, nu=1.0)
+    R = sd.rhs(torch_cuda.from_numpy(np.ascontiguousarray(u[:, None])).to("cuda")).cpu().numpy()[:, 0]
+    sd.close()
+    Ro = C.rhs(u, nel, Xg, p, scheme, nu=1.0)
+    err = np.abs(R - Ro).max() / np.abs(Ro).max()
+    print(f"16^3 curved {scheme}: {err:.2e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "ssprk54"])
+def test_curvilinear_time_steps(torch_cuda, integrator):
+    nel, p, dt, nu = (3, 3, 2), 3, 2e-3, 0.7
+    Xg = meshes(nel)["curved"]
+    n = p + 1
+    u0 = np.random.Generator(np.random.PCG64(12)).normal(size=(int(np.prod(nel)), n, n, n))
+    sd = make(torch_cuda, nel, p, "compact", Xg, nu=nu, integrator=integrator)
+    u = torch_cuda.from_numpy(u0[:, None].copy()).to("cuda")
+    for _ in range(2):
+        sd.rk_step(u, dt)
+    got = u.cpu().numpy()[:, 0]
+    sd.close()
+    f = lambda v: C.rhs(v, nel, Xg, p, "compact", nu=nu)
+    if integrator == "ssprk54":
+        ref = ssprk.integrate(f, u0, dt, 2)
+    else:
+        ref = u0
+        for _ in range(2):
+            k1 = f(ref)
+            k2 = f(ref + 0.5 * dt * k1)
+            k3 = f(ref + 0.5 * dt * k2)
+            k4 = f(ref + dt * k3)
+            ref = ref + dt / 6.0 * (((k1 + 2.0 * k2) + 2.0 * k3) + k4)
+    change = np.abs(ref - u0).max()
+    err = np.abs(got - ref).max() / change
+    floor = 2 * 10 * np.finfo(np.float64).eps * np.abs(u0).max() / change
+    print(f"{integrator}: {err:.2e} of the change (floor {floor:.1e})")
+    assert err < max(1e-12, floor)
+
+
+def test_curvilinear_argument_checks(torch_cuda):
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd.sd import SDError
+    nel, p = (2, 2, 2), 2
+    good = W.mesh_nodes(nel, *BOX, q=1)
+    lo, hi = W.tgv_domain()
+    for kw in (dict(physics="ns", lo=lo, hi=hi), dict(physics="diffusion", precision="fp32", lo=lo, hi=hi),
+               dict(physics="diffusion", eta_ip=0.1, lo=lo, hi=hi)):
+        sd = SD(nel, p, scheme="compact", **kw)
+        with pytest.raises(SDError):
+            sd.set_geometry(good)
+        sd.close()
+    sd = SD(nel, p, scheme="compact", physics="diffusion", lo=lo, hi=hi)
+    with pytest.raises(ValueError):
+        sd.set_geometry(good[:-1])
+    bad = good.copy()
+    bad[3] = bad[3][:, :, ::-1]                     # one element mirrored: det J < 0
+    with pytest.raises(SDError):
+        sd.set_geometry(bad)
+    # a failed call leaves the context usable; a good one replaces the geometry
+    sd.set_geometry(W.mesh_nodes(nel, *BOX, q=2, displacement=W.periodic_wave_displacement(0.2)))
+    sd.set_geometry(good)
+    u = np.random.Generator(np.random.PCG64(1)).normal(size=(8, 3, 3, 3))
+    R = sd.rhs(torch_cuda.from_numpy(u[:, None]).to("cuda")).cpu().numpy()[:, 0]
+    sd.close()
+    Ro = C.rhs(u, nel, good, p, "compact", nu=1.0)
+    assert np.abs(R - Ro).max() < 1e-12 * np.abs(Ro).max()

@@ -96,6 +96,7 @@ def test_null_pointers(lib):
     assert lib.sd_rhs(None, None, None) == -1
     assert lib.sd_rk_step(None, None, 0.1) == -1
     assert lib.sd_stable_dt(None, None, 0.3, None) == -1
+    assert lib.sd_set_geometry(None, None, 1) == -1
 
 
 @pytest.mark.parametrize("cfg,ntheta,rc", [
