@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--precisions", default="fp32,fp64", help="fp32 and fp64 always for the JSON line; bf16x3 optional")
     ap.add_argument("--bloch-theta", type=int, default=1 << 16,
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
-    ap.add_argument("--bloch-only", action="store_true", help="time only the Bloch sweep and print its record")
+    ap.add_argument("--curv-nel", type=int, default=32,
+                    help="elements per direction of the curvilinear diffusion workload (0: skip it)")
+    ap.add_argument("--only", choices=["bloch", "curvilinear"], default=None,
+                    help="time only that workload and print its record")
     return ap.parse_args()
 
 
@@ -70,12 +73,15 @@ def parse():
 TRAFFIC_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispatch.inc", "sd_operators.cpp"]
 
 
-def sources_sha256():
+CURV_TRAFFIC_SOURCES = ["sd_curv_kernel.h", "sd_curv.inc", "sd_internal.h", "sd_operators.cpp"]
+
+
+def sources_sha256(names=None):
     import hashlib
     from paper_2608_09615_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     h.update(" ".join(HIPCC_FLAGS).encode())
-    for name in TRAFFIC_SOURCES:
+    for name in names or TRAFFIC_SOURCES:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2608_09615_amd", "csrc", name), "rb") as f:
             h.update(f.read())
@@ -235,6 +241,63 @@ def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
                          "kernels": "k_bloch_lane_cm (combined mode)"}}
 
 
+def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20):
+    """Linear diffusion on curvilinear hexahedra (degree-2 elements of a
+    periodic box moved by a smooth wave of amplitude 0.3), FP64, one RHS per
+    step.  Roofline: HBM, with the algorithmic bytes per element the state
+    in and the RHS out (2 x 8 n^3) plus the metric terms the kernels must
+    read (S rows at 3 (n+1) n^2 flux points, 1/det J at n^3 points: 8 (9 (n+1)
+    n^2 + n^3))."""
+    import numpy as np
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd import workloads as W
+    N = args.curv_nel
+    nel = (N,) * 3
+    n = p + 1
+    box = ((0.0, 0.0, 0.0), (2 * math.pi,) * 3)
+    Xg = W.mesh_nodes(nel, *box, q=2, displacement=W.periodic_wave_displacement(0.3))
+    sd = SD(nel, p, scheme=scheme, physics="diffusion", lo=[0.0] * 3, hi=[1.0] * 3)
+    sd.set_geometry(Xg)
+    x = W.map_points(Xg, p)
+    u = torch.from_numpy(np.ascontiguousarray((np.sin(x[..., 0]) * np.sin(x[..., 1]) * np.sin(x[..., 2]))[:, None]))
+    u = u.to("cuda")
+    out = torch.empty_like(u)
+    for _ in range(3):
+        sd.rhs(u, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sd.rhs(u, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sd.close()
+    dof = N ** 3 * n ** 3
+    bytes_el = 16.0 * n ** 3 + 8.0 * (9 * (n + 1) * n * n + n ** 3)
+    gbs = bytes_el * N ** 3 / (ms * 1e-3) / 1e9
+    return {"config": f"linear diffusion, {N}^3 degree-2 hexahedra (periodic box, wave displacement 0.3), "
+                      f"p={p} {scheme}, FP64",
+            "gdofs_per_rhs": dof / ms / 1e6, "ms_per_rhs": ms,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": curv_traffic(N, p, scheme),
+                         "traffic_unit": "B per RHS", "kernels": "k_cv_traces + k_cv_grad + k_cv_rhs"}}
+
+
+def curv_traffic(N, p, scheme):
+    """HBM bytes per curvilinear RHS from the committed counter record, or
+    None for another workload or once a source it is keyed to has changed."""
+    path = os.path.join(ROOT, "profiles", "curv_traffic_32cubed_p3.json")
+    if not (N == 32 and p == 3 and scheme == "compact" and os.path.exists(path)):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if sources_sha256(CURV_TRAFFIC_SOURCES) != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_rhs"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -246,8 +309,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.bloch_only:
+    if args.only == "bloch":
         print(json.dumps({"bloch": bloch_bench(torch, args)}), flush=True)
+        return
+    if args.only == "curvilinear":
+        print(json.dumps({"curvilinear": curvilinear_bench(torch, args)}), flush=True)
         return
     nel = (args.nel,) * 3
     U0 = W.tgv_state(nel, args.p)
@@ -322,6 +388,8 @@ def main():
                          "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "bf16x3")}
     if args.bloch_theta > 0:
         rec["bloch"] = bloch_bench(torch, args)
+    if args.curv_nel > 0:
+        rec["curvilinear"] = curvilinear_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0)
     print(json.dumps(rec), flush=True)
