@@ -8,7 +8,7 @@
 // the n + 1 flux points of a line by r.  Face arrays use the same q, so the
 // two elements of a face index its points alike.
 //
-// Three kernels, one element per block:
+// Three kernels, one element per block (cv_threads<N>() lanes):
 //   k_cv_traces  the solution at the six faces, T[e][f][q] (f = 2 d + s);
 //   k_cv_grad    common solution at the faces, the continuous solution at
 //                the flux points, the auxiliary variable v_m at the
@@ -24,7 +24,10 @@
 
 namespace sd {
 
-constexpr int kCvThreads = 256;
+// one element per block: a single wavefront for n <= 4 (barriers stay
+// cheap and many blocks fit a CU), more lanes for the larger elements
+template <int N>
+__host__ __device__ constexpr int cv_threads() { return N <= 4 ? 64 : (N <= 5 ? 128 : 256); }
 
 template <int N>
 __device__ __forceinline__ int cv_point(int d, int q, int c) {
@@ -50,7 +53,7 @@ __device__ __forceinline__ void cv_line_of(int pt, int d, int &q, int &c) {
 }
 
 template <int N>
-__global__ void __launch_bounds__(kCvThreads) k_cv_traces(const double *__restrict__ U, double *__restrict__ T,
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_traces(const double *__restrict__ U, double *__restrict__ T,
                                                           const double *__restrict__ ops, long long ne) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N;
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(kCvThreads) k_cv_traces(const double *__restri
 }
 
 template <int N>
-__global__ void __launch_bounds__(kCvThreads) k_cv_grad(const double *__restrict__ U, const double *__restrict__ T,
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__restrict__ U, const double *__restrict__ T,
                                                         const double *__restrict__ Sf, const double *__restrict__ Jinv,
                                                         const double *__restrict__ ops, KArgs a, int compact,
                                                         double *__restrict__ VF, double *__restrict__ VS) {
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(kCvThreads) k_cv_grad(const double *__restrict
 }
 
 template <int N>
-__global__ void __launch_bounds__(kCvThreads) k_cv_rhs(const double *__restrict__ VF, const double *__restrict__ VS,
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_rhs(const double *__restrict__ VF, const double *__restrict__ VS,
                                                        const double *__restrict__ Sf, const double *__restrict__ Jinv,
                                                        const double *__restrict__ ops, KArgs a,
                                                        double *__restrict__ dudt) {
