@@ -75,12 +75,18 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
                                                         double *__restrict__ VF, double *__restrict__ VS) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF;
-  __shared__ double su[NP], sT[6 * NF], sUh[6 * NF], sUF[3 * NL], sV[3 * NP];
+  // the element's metric rows ([d][q][r][m]) are read by every point of a
+  // line: staged in LDS for n >= 5, where that beats the L2 (for n <= 4 the
+  // extra LDS and load phase cost more than the misses they save)
+  constexpr bool kStageS = N >= 5;
+  __shared__ double su[NP], sT[6 * NF], sUh[6 * NF], sUF[3 * NL], sV[3 * NP], sS[kStageS ? 9 * NL : 1];
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x;
-  const double *S = Sf + e * 9 * NL;       // [d][q][r][m]
   const double *ji = Jinv + e * NP;
+  const double *S = kStageS ? sS : Sf + e * 9 * NL;
+  if constexpr (kStageS)
+    for (int t = tid; t < 9 * NL; t += blockDim.x) sS[t] = Sf[e * 9 * NL + t];
   for (int t = tid; t < NP; t += blockDim.x) su[t] = U[e * NP + t];
   for (int t = tid; t < 6 * NF; t += blockDim.x) {
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
