@@ -67,6 +67,20 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
             "t": t, "ke": ke, "enstrophy": ens, "wall_s": wall}
 
 
+def stability(nel, p, scheme, precision="fp32", Re=1600.0, t_end=20.0, dt_out=0.5, log=print, cfl=None):
+    """Run the TGV to t_end and report whether it stays finite (the paper's
+    stability tables): {"stable": bool, "t_fail": first output time at which
+    the state was non-finite or None, "wall_s": ...}."""
+    try:
+        r = history(nel, p, scheme, precision, Re, t_end, dt_out, log, cfl=cfl)
+        return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": True,
+                "t_fail": None, "wall_s": r["wall_s"], "ke_end": r["ke"][-1]}
+    except FloatingPointError as err:
+        t_fail = float(str(err).split("t=")[-1])
+        return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": False,
+                "t_fail": t_fail, "wall_s": None, "ke_end": None}
+
+
 def compare(run, ref):
     """max_t |KE - KE_ref| / KE_ref(0) and max_t |ens - ens_ref| / max_t ens_ref."""
     ke = max(abs(a - b) for a, b in zip(run["ke"], ref["ke"])) / ref["ke"][0]
@@ -86,9 +100,21 @@ def main(argv=None):
     ap.add_argument("--precisions", default="fp64,fp32", help="the first one is the reference")
     ap.add_argument("--integrator", default="rk4", choices=["rk4", "ssprk54"])
     ap.add_argument("--cfl", type=float, default=None, help="adaptive step with this Courant number")
+    ap.add_argument("--stability", action="store_true",
+                    help="run BR1 and compact in the first precision only and report whether each stays finite")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
+    if a.stability:
+        pr = a.precisions.split(",")[0]
+        res = [stability(a.nel, a.p, sch, pr, a.Re, a.t_end, a.dt_out, log, a.cfl) for sch in ("br1", "compact")]
+        for r in res:
+            log(f"tgv stability: Re={a.Re:g} {a.nel}^3 p={a.p} ({a.nel * (a.p + 1)}^3 DoF) {r['scheme']} {pr}: "
+                + ("stable" if r["stable"] else f"unstable (non-finite by t={r['t_fail']:.2f})"))
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f)
+        return
     runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log, a.integrator, a.cfl)
             for pr in a.precisions.split(",")]
     res = {"runs": runs, "errors": {r["precision"]: compare(r, runs[0]) for r in runs[1:]}}

@@ -103,7 +103,7 @@ def test_3d_ns_parity_fp64(torch_cuda, oracle_lib, scheme, p):
 
 
 @pytest.mark.parametrize("scheme", ["br1", "compact"])
-@pytest.mark.parametrize("p", [1, 3, 5])
+@pytest.mark.parametrize("p", [1, 3, 5, 7])
 def test_3d_ns_parity_fp32(torch_cuda, oracle_lib, scheme, p):
     prm = oracle_lib.make_params("ns", Re=1600.0)
     lo, hi = W.tgv_domain()
@@ -117,10 +117,10 @@ def test_3d_ns_parity_fp32(torch_cuda, oracle_lib, scheme, p):
 
 
 @pytest.mark.parametrize("scheme", ["br1", "compact"])
-@pytest.mark.parametrize("p", [1, 3, 4, 5])
+@pytest.mark.parametrize("p", [1, 3, 4, 5, 7])
 def test_3d_ns_parity_bf16x3(torch_cuda, oracle_lib, scheme, p):
     """BF16x3 split-precision path (matrix-core gradient and divergence)
-    against the FP64 oracle; p = 4 and 5 take two row and K chunks."""
+    against the FP64 oracle; p = 4, 5 and 7 take two row and K chunks."""
     prm = oracle_lib.make_params("ns", Re=1600.0)
     lo, hi = W.tgv_domain()
     nel = (4, 3, 5)
@@ -132,6 +132,17 @@ def test_3d_ns_parity_bf16x3(torch_cuda, oracle_lib, scheme, p):
     print(f"bf16x3 NS p={p} {scheme}: normwise relative error {err:.3e}, per variable "
           + " ".join(f"{e:.2e}" for e in per_var))
     assert err < BF16X3_TOL_NS
+
+
+def test_ns_p7_runs_in_fp32_only(torch_cuda):
+    """p = 7 needs one element's 24 480 LDS values per block: 98 KB in FP32
+    and BF16x3, 191 KB in FP64, beyond the 160 KB of a compute unit."""
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd.sd import SDError
+    lo, hi = W.tgv_domain()
+    with pytest.raises(SDError, match="LDS"):
+        SD((2, 2, 2), 7, scheme="compact", physics="ns", precision="fp64", lo=lo, hi=hi)
+    SD((2, 2, 2), 7, scheme="compact", physics="ns", precision="fp32", lo=lo, hi=hi).close()
 
 
 @pytest.mark.parametrize("scheme,width", [("compact", 19), ("br1", 25)])
