@@ -5,7 +5,9 @@
  *     du/dt + div F(u, grad u) = 0,
  * written as the first-order system with the auxiliary gradient v = grad u
  * and mapped to the reference hexahedron (Lodato & Tonicello, section 2,
- * eqs. ns and ns:mapped/adj:f), on uniform periodic Cartesian meshes.  The
+ * eqs. ns and ns:mapped/adj:f), on structured periodic hexahedral meshes:
+ * uniform Cartesian ones, or (3-D diffusion) curvilinear elements given by
+ * their node coordinates (sd_set_geometry).  The
  * auxiliary gradient is reconstructed either with the standard BR1-type
  * centred treatment (section 2.1: common solution eq. c:flux, gradient
  * eqs. w:e/v:e, common gradient eq. aux:v:int; five-element stencil in 1-D)
@@ -118,7 +120,8 @@ int sd_params_default(sd_params *prm);
 
 /* Create a context for polynomial degree p (n = p + 1 points) and scheme
  * (sd_scheme).  Supported: dim 1 with diffusion or PME, p in [1, 8]; dim 3
- * with diffusion or Navier-Stokes, p in [1, 6] (FP64) or [1, 6] (FP32).
+ * with diffusion, p in [1, 6]; dim 3 Navier-Stokes, p in [1, 6] (FP64) or
+ * [1, 7] (FP32, BF16x3); anything else returns SD_EUNSUPPORTED.
  * stream: a hipStream_t (NULL = the default stream).  Allocates the
  * operators and the scratch buffers (face traces, RK registers) on the
  * current device; the context owns them until sd_free. */
