@@ -27,6 +27,14 @@ def step_size(nel, p, dt_out, Ma=0.1, cfl=0.3):
     return dt_out / k, k
 
 
+class NonFiniteState(FloatingPointError):
+    """The state turned non-finite; t is the first output time that saw it."""
+
+    def __init__(self, msg, t):
+        super().__init__(msg)
+        self.t = t
+
+
 def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, dt_out=0.1, log=print,
             integrator="rk4", cfl=None):
     """KE and enstrophy every dt_out up to t_end, and the wall time of the
@@ -52,7 +60,7 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
         steps += k
         d = sd.diagnostics(u)
         if d["nonfinite"]:
-            raise FloatingPointError(f"{precision} run turned non-finite before t={i * dt_out:.2f}")
+            raise NonFiniteState(f"{precision} run turned non-finite before t={i * dt_out:.2f}", i * dt_out)
         t.append(i * dt_out)
         ke.append(d["ke"])
         ens.append(d["enstrophy"])
@@ -75,8 +83,8 @@ def stability(nel, p, scheme, precision="fp32", Re=1600.0, t_end=20.0, dt_out=0.
         r = history(nel, p, scheme, precision, Re, t_end, dt_out, log, cfl=cfl)
         return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": True,
                 "t_fail": None, "wall_s": r["wall_s"], "ke_end": r["ke"][-1]}
-    except FloatingPointError as err:
-        t_fail = float(str(err).split("t=")[-1])
+    except NonFiniteState as err:
+        t_fail = err.t
         return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": False,
                 "t_fail": t_fail, "wall_s": None, "ke_end": None}
 
