@@ -170,9 +170,11 @@ struct NsSmem {
 // Launch shape of k_rhs_ns, fixed per instantiation so that the work-item
 // index arithmetic divides by compile-time constants: as many elements per
 // block as fit the LDS target (at most one full block of solution points and
-// kNsMaxEpb), and 4 n^2 threads per element (256 for four p = 3 elements):
-// with the face pass at ~137 VGPRs (three wavefronts per SIMD) this fills the
-// compute unit as far as the LDS of three such blocks allows.
+// kNsMaxEpb), and min(8 n^2, 256) threads per element, capped by the launch
+// bound (512 for four FP32 p = 3 elements, 256 for two FP64 ones): the LDS
+// limits the elements a compute unit holds, so more lanes per element is
+// what raises the wavefronts per SIMD (measured: p = 3 FP32 +5%, FP64 +9%,
+// p = 5 FP32 +11%, FP64 +17%, BF16x3 +41% over 4 n^2 lanes).
 template <int N, typename R>
 __host__ __device__ constexpr int ns_epb() {
 #ifdef SD_NS_EPB
@@ -187,7 +189,7 @@ __host__ __device__ constexpr int ns_epb() {
 }
 template <int N, typename R>
 __host__ __device__ constexpr int ns_threads() {
-  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : 4 * N * N;
+  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : (8 * N * N < 256 ? 8 * N * N : 256);
   const int t = (ns_epb<N, R>() * tpe + 63) / 64 * 64;
   return t < ns_max_threads<N, R>() ? t : ns_max_threads<N, R>();
 }
