@@ -170,11 +170,8 @@ struct NsSmem {
 // Launch shape of k_rhs_ns, fixed per instantiation so that the work-item
 // index arithmetic divides by compile-time constants: as many elements per
 // block as fit the LDS target (at most one full block of solution points and
-// kNsMaxEpb), and min(8 n^2, 256) threads per element, capped by the launch
-// bound (512 for four FP32 p = 3 elements, 256 for two FP64 ones): the LDS
-// limits the elements a compute unit holds, so more lanes per element is
-// what raises the wavefronts per SIMD (measured: p = 3 FP32 +5%, FP64 +9%,
-// p = 5 FP32 +11%, FP64 +17%, BF16x3 +41% over 4 n^2 lanes).
+// kNsMaxEpb), and ns_lanes threads per element, capped by the launch bound
+// (512 for four FP32 p = 3 elements, 256 for two FP64 ones).
 template <int N, typename R>
 __host__ __device__ constexpr int ns_epb() {
 #ifdef SD_NS_EPB
@@ -187,9 +184,18 @@ __host__ __device__ constexpr int ns_epb() {
   if (e > kNsMaxEpb) e = kNsMaxEpb;
   return e < 1 ? 1 : (int)e;
 }
+// Lanes per element, measured per degree and precision (TGV workloads of
+// 1.9-17 M solution points): the block's elements are fixed by the LDS, and
+// the lanes decide how its wavefronts pack next to the VGPR limit, which is
+// not monotone (n = 4: 128 beats 64 by 5-9%; n = 5: 200 loses 45% to 100).
+template <int N, typename R>
+__host__ __device__ constexpr int ns_lanes() {
+  constexpr bool f64 = sizeof(R) == 8;
+  return N == 2 ? 32 : N == 3 ? (f64 ? 36 : 72) : N == 4 ? 128 : N == 5 ? 100 : N == 6 ? 256 : 4 * N * N;
+}
 template <int N, typename R>
 __host__ __device__ constexpr int ns_threads() {
-  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : (8 * N * N < 256 ? 8 * N * N : 256);
+  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : ns_lanes<N, R>();
   const int t = (ns_epb<N, R>() * tpe + 63) / 64 * 64;
   return t < ns_max_threads<N, R>() ? t : ns_max_threads<N, R>();
 }
