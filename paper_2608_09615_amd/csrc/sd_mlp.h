@@ -229,12 +229,19 @@ struct ClosureNorm {
   float max_ratio;        // <= 0: no magnitude bound
 };
 
+// a[v] for a run-time v in [0, 5) by selects: the constant-index reads stay
+// scalar loads of the kernel arguments (an indexed read would be a vector
+// load from the argument segment per value)
+__device__ __forceinline__ double pick5(const float (&a)[5], int v) {
+  return (double)(v == 0 ? a[0] : v == 1 ? a[1] : v == 2 ? a[2] : v == 3 ? a[3] : a[4]);
+}
+
 __global__ void k_closure_input(const double *__restrict__ u, float *__restrict__ X, long long n, int np,
                                 ClosureNorm cn) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int v = (int)((i / np) % 5);
-  X[i] = (float)((u[i] - (double)cn.shift[v]) / (double)cn.scale[v]);
+  X[i] = (float)((u[i] - pick5(cn.shift, v)) / pick5(cn.scale, v));
 }
 
 }  // namespace sd
