@@ -103,17 +103,21 @@ def test_filter_matches_reference(torch_cuda, ratio, p, nelc):
     assert np.abs(Uc - Uo).max() < 1e-13 * np.abs(Uo).max()
 
 
-def test_closure_in_solver(torch_cuda, oracle_lib):
+@pytest.mark.parametrize("n_h,nel", [(32, (3, 2, 2)), (128, (5, 2, 2)), (256, (3, 3, 2))])
+def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
     """R_closure = R_plain + out_scale * net(normalised u) per element; a
     correction larger than max_ratio R is discarded for that element, and
-    max_ratio = 0 keeps every finite correction."""
+    max_ratio = 0 keeps every finite correction.  12 and 20 elements: one
+    padded block, and a full block plus a ragged one, of the single-launch
+    kernel; 256 hidden units take the layer-by-layer path."""
+    print(f"[closure in solver] n_h={n_h} nel={nel}", flush=True)
     torch = torch_cuda
     from paper_2608_09615_amd import SD
-    nel, p = (3, 2, 2), 3
+    p = 3
     lo, hi = W.tgv_domain()
     U = W.perturbed_tgv_state(nel, p, seed=11, noise=1e-3)
     nve = 5 * 64
-    net, prm = make_net(torch, nve, 32, nve, seed=8, bias=0.0)
+    net, prm = make_net(torch, nve, n_h, nve, seed=8, bias=0.0)
     shift = [1.0, 0.0, 0.0, 0.0, 178.57]
     scale = [0.01, 0.5, 0.5, 0.5, 0.2]
     Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, "compact", oracle_lib.make_params("ns"))
@@ -142,6 +146,44 @@ def test_closure_in_solver(torch_cuda, oracle_lib):
         assert d.max() < 2e-2 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()
         assert np.mean(d < 1e-4 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()) > 0.999
         sd.close()
+
+
+@pytest.mark.parametrize("n_h", [128, 256])
+def test_closure_rk_step_matches_stage_sequence(torch_cuda, n_h):
+    """sd_rk_step with a closure applies each RK4 stage in the closure's
+    epilogue (the stage state updated in place): it matches the classical
+    RK4 combination of closure right-hand sides evaluated one by one."""
+    print(f"[closure rk step] n_h={n_h}", flush=True)
+    torch = torch_cuda
+    from paper_2608_09615_amd import SD
+    nel, p, dt = (3, 3, 2), 3, 2e-3
+    lo, hi = W.tgv_domain()
+    U = W.perturbed_tgv_state(nel, p, seed=5, noise=1e-3)
+    nve = 5 * 64
+    net, _ = make_net(torch, nve, n_h, nve, seed=9, bias=0.1)
+    sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+    u0 = torch.from_numpy(U).to("cuda")
+    R0 = sd.rhs(u0)
+    u_plain = u0.clone()
+    sd.rk_step(u_plain, dt)
+    sd.closure_set(net, [1.0, 0.0, 0.0, 0.0, 178.57], [0.01, 0.5, 0.5, 0.5, 0.2], [1e-3] * 5, max_ratio=0.0)
+    k1 = sd.rhs(u0)
+    Cmax = (k1 - R0).abs().max().item()
+    assert Cmax > 1e-6
+    k2 = sd.rhs(u0 + 0.5 * dt * k1)
+    k3 = sd.rhs(u0 + 0.5 * dt * k2)
+    k4 = sd.rhs(u0 + dt * k3)
+    ref = u0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    u = u0.clone()
+    sd.rk_step(u, dt)
+    assert sd.closure_rejected() == 0
+    d = (u - ref).abs().max().item()
+    # stage states may differ in the last bit (fused multiply-add), which can
+    # move a BF16 rounding of a network input: bar as in the RHS test, times dt
+    assert d < dt * (2e-2 * Cmax + 1e-11 * R0.abs().max().item()) + 1e-14 * u0.abs().max().item()
+    # the closure does change the step, by far more than that bar
+    assert (u - u_plain).abs().max().item() > 0.1 * dt * Cmax
+    sd.close()
 
 
 def test_training_reduces_loss(torch_cuda):
