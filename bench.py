@@ -62,7 +62,9 @@ def parse():
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
     ap.add_argument("--curv-nel", type=int, default=32,
                     help="elements per direction of the curvilinear diffusion workload (0: skip it)")
-    ap.add_argument("--only", choices=["bloch", "curvilinear"], default=None,
+    ap.add_argument("--closure-nel", type=int, default=16,
+                    help="elements per direction of the learned-closure timing (0: skip it)")
+    ap.add_argument("--only", choices=["bloch", "curvilinear", "closure"], default=None,
                     help="time only that workload and print its record")
     return ap.parse_args()
 
@@ -285,6 +287,52 @@ def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20):
                          "traffic_unit": "B per RHS", "kernels": "k_cv_traces + k_cv_grad + k_cv_rhs"}}
 
 
+def closure_bench(torch, args, p=3, hidden=128, reps=200):
+    """Cost of the learned closure inside the right-hand side: the compact
+    FP32 Navier-Stokes RHS of the Taylor-Green state at Re = 5000 on N^3
+    elements, p = 3, timed without and with the closure network
+    (5 n^3 -> hidden -> hidden -> 5 n^3, GELU, seeded weights; the cost
+    does not depend on their values).  The closure adds one launch per RHS
+    (k_closure_fused); its figure is the difference of the two times, and
+    the achieved rate is that of the network's matrix products in it."""
+    from paper_2608_09615_amd import SD, workloads as W
+    from paper_2608_09615_amd import closure as CL
+    from paper_2608_09615_amd.sd import Mlp
+    N = args.closure_nel
+    nel = (N,) * 3
+    nve = 5 * (p + 1) ** 3
+    lo, hi = W.tgv_domain()
+    u = torch.from_numpy(W.tgv_state(nel, p)).to("cuda")
+    stream = torch.cuda.current_stream()
+    us = {}
+    for on in (False, True):
+        sd = SD(nel, p, scheme="compact", physics="ns", precision="fp32", lo=lo, hi=hi, Re=5000.0)
+        if on:
+            net = Mlp(nve, hidden, nve, torch.from_numpy(CL.init_params_flat(nve, hidden, nve, seed=1)).to("cuda"))
+            sd.closure_set(net, [1.0, 0.0, 0.0, 0.0, 178.57], [0.01, 0.5, 0.5, 0.5, 0.2], [1e-6] * 5, max_ratio=1.0)
+        out = torch.empty_like(u)
+        for _ in range(5):
+            sd.rhs(u, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            sd.rhs(u, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us[on] = e0.elapsed_time(e1) / reps * 1e3
+        if on:
+            rejected = sd.closure_rejected()
+        sd.close()
+    extra = us[True] - us[False]
+    flop = 2.0 * (nve * hidden + hidden * hidden + hidden * nve) * N ** 3
+    return {"config": f"compact NS RHS, TGV state, {N}^3 elements, p={p}, FP32, Re=5000; network "
+                      f"{nve}-{hidden}-{hidden}-{nve} GELU on BF16 matrix cores",
+            "us_per_rhs": us[False], "us_per_rhs_with_closure": us[True], "closure_us": extra,
+            "closure_tflops": flop / (extra * 1e-6) / 1e12, "rejected_elements": rejected,
+            "kernel": "k_closure_fused"}
+
+
 def curv_traffic(N, p, scheme):
     """HBM bytes per curvilinear RHS from the committed counter record, or
     None for another workload or once a source it is keyed to has changed."""
@@ -314,6 +362,9 @@ def main():
         return
     if args.only == "curvilinear":
         print(json.dumps({"curvilinear": curvilinear_bench(torch, args)}), flush=True)
+        return
+    if args.only == "closure":
+        print(json.dumps({"closure": closure_bench(torch, args)}), flush=True)
         return
     nel = (args.nel,) * 3
     U0 = W.tgv_state(nel, args.p)
@@ -390,6 +441,8 @@ def main():
         rec["bloch"] = bloch_bench(torch, args)
     if args.curv_nel > 0:
         rec["curvilinear"] = curvilinear_bench(torch, args)
+    if args.closure_nel > 0:
+        rec["closure"] = closure_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0)
     print(json.dumps(rec), flush=True)
