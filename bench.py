@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0     # dense BF16 matrix cores
 
 # Algorithmic work per solution point and RHS at p = 3, Navier-Stokes:
 # contractions 18 nv (n+1) MAC = 450 MAC = 900 flop (interpolation to the three
@@ -326,11 +327,18 @@ def closure_bench(torch, args, p=3, hidden=128, reps=200):
         sd.close()
     extra = us[True] - us[False]
     flop = 2.0 * (nve * hidden + hidden * hidden + hidden * nve) * N ** 3
+    # algorithmic HBM bytes of the launch: the state and R read, R written
+    # (FP64), and the BF16 weights and FP32 biases once
+    nbytes = 3 * 8.0 * nve * N ** 3 + 2.0 * (nve * hidden + hidden * hidden + hidden * nve) + 4.0 * (2 * hidden + nve)
+    gbs = nbytes / (extra * 1e-6) / 1e9
     return {"config": f"compact NS RHS, TGV state, {N}^3 elements, p={p}, FP32, Re=5000; network "
                       f"{nve}-{hidden}-{hidden}-{nve} GELU on BF16 matrix cores",
             "us_per_rhs": us[False], "us_per_rhs_with_closure": us[True], "closure_us": extra,
             "closure_tflops": flop / (extra * 1e-6) / 1e12, "rejected_elements": rejected,
-            "kernel": "k_closure_fused"}
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernels": "k_closure_fused",
+                         "mfma_frac_bf16": flop / (extra * 1e-6) / 1e12 / PEAK_BF16_TFLOPS,
+                         "duration": "closure_us (RHS time with the closure minus without)"}}
 
 
 def curv_traffic(N, p, scheme):
