@@ -112,12 +112,34 @@ def _neighbour(nel, d, s):
     return c[0] + Nx * (c[1] + Ny * c[2])
 
 
-def rhs(u, nel, Xg, p, scheme="compact", nu=1.0):
-    """du/dt for u[e][k][j][i] on the mesh of node coordinates Xg."""
+def face_det(Xg, p):
+    """det J at the flux points of each family d ([E, ...], the family's
+    flux axis in place of its solution axis): at its two ends, the points of
+    the faces normal to d."""
+    xs, _, xf, _, _ = operators(p)
+    out = []
+    for d in range(3):
+        pts = [xs, xs, xs]
+        pts[d] = xf
+        out.append(np.linalg.det(jacobian(Xg, pts[0], pts[1], pts[2])))
+    return out
+
+
+def rhs(u, nel, Xg, p, scheme="compact", nu=1.0, eta_ip=0.0):
+    """du/dt for u[e][k][j][i] on the mesh of node coordinates Xg.
+
+    eta_ip > 0 adds the interior penalty of section 3 to the common gradient
+    at every interface: its component along the unit normal n = S_d / |S_d|
+    gains tau (u_R - u_L), u_R the trace of the element on the +xi_d side,
+    with tau = eta_ip (p+1)^2 / h and 1/h = |S_d| max(J^-1_L, J^-1_R) / 2 at
+    the face point (on an affine Cartesian element |S_d| J^-1 = 2 / h_d,
+    the element size normal to the face; the larger J^-1 takes the smaller
+    of the two sizes)."""
     u = np.asarray(u, dtype=np.float64)
     _, _, _, L, M = operators(p)
     S, detJ = metrics(Xg, p)
     Jinv = 1.0 / detJ
+    detJF = face_det(Xg, p) if eta_ip else None
     nbr = {(d, s): _neighbour(nel, d, s) for d in range(3) for s in (0, 1)}
     # 1. discontinuous solution at the flux points of each family
     uF = [_along(u, d, L) for d in range(3)]
@@ -165,6 +187,13 @@ def rhs(u, nel, Xg, p, scheme="compact", nu=1.0):
         for s in (0, 1):
             other = vface[(d, 1 - s)][nbr[(d, s)]]
             vh = 0.5 * (other + vface[(d, s)]) if s == 0 else 0.5 * (vface[(d, s)] + other)
+            if eta_ip:
+                # interior penalty: tau (u_R - u_L) n = eta (p+1)^2 max(J^-1) / 2 (u_R - u_L) S_d
+                t_oth = T[(d, 1 - s)][nbr[(d, s)]]
+                jump = T[(d, s)] - t_oth if s == 0 else t_oth - T[(d, s)]
+                jmax = np.maximum(1.0 / _end(detJF[d], d, s), 1.0 / _end(detJF[d], d, 1 - s)[nbr[(d, s)]])
+                coef = eta_ip * (p + 1) ** 2 / 2.0 * jmax * jump
+                vh = vh + np.stack([coef * _end(S[d][..., d, m], d, s) for m in range(3)], axis=1)
             for m in range(3):
                 sub = vF[:, m]
                 _set_end(sub, d, s, vh[:, m])

@@ -114,3 +114,46 @@ def test_refinement_on_a_curved_mesh(scheme):
         u = np.sin(x[..., 0]) * np.sin(x[..., 1]) * np.sin(x[..., 2])
         errs.append(np.abs(C.rhs(u, nel, Xg, 3, scheme) + 3.0 * u).max())
     assert errs[1] < 0.05 and errs[0] / errs[1] > 2 ** 1.5
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_interior_penalty_on_affine_nodes_is_the_cartesian_one(oracle_lib, scheme, p):
+    """Section 3's penalty written with the metric terms (tau n = eta (p+1)^2
+    max(J^-1) S_d / 2 (u_R - u_L)) reduces on affine elements of a box with
+    three different element sizes to the Cartesian tau = eta (p+1)^2 / h_d
+    of the C reference, for degree-1 and degree-2 node sets."""
+    nel, lo, hi = (3, 4, 2), (0.0, 0.0, 0.0), (1.0, 2.0, 1.5)
+    U = W.random_scalar_3d(nel, p, seed=6)
+    prm = oracle_lib.make_params("diffusion", nu=0.8, eta_ip=0.35)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)[:, 0]
+    R0 = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, oracle_lib.make_params("diffusion", nu=0.8))[:, 0]
+    assert np.abs(Ro - R0).max() > 1e-2 * np.abs(R0).max()          # the penalty matters here
+    for q in (1, 2):
+        R = C.rhs(U[:, 0], nel, W.mesh_nodes(nel, lo, hi, q=q), p, scheme, nu=0.8, eta_ip=0.35)
+        assert np.abs(R - Ro).max() < 1e-13 * np.abs(Ro).max()
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_interior_penalty_rotation_and_conservation(scheme):
+    """With the penalty on: a rigidly rotated mesh gives the same RHS (the
+    penalty acts along the physical normal), and on a curved mesh the
+    J-weighted integral of the RHS vanishes (both elements of a face see the
+    same penalty, the larger J^-1 of the two sides)."""
+    p = 3
+    nel, lo, hi = (3, 2, 4), (0.0, 0.0, 0.0), (1.5, 1.0, 2.0)
+    U = W.random_scalar_3d(nel, p, seed=12)[:, 0]
+    R = C.rhs(U, nel, W.mesh_nodes(nel, lo, hi, q=1), p, scheme, eta_ip=0.5)
+    Rr = C.rhs(U, nel, W.mesh_nodes(nel, lo, hi, q=1, rotation=rotation(0.3, -0.8, 1.2)), p, scheme, eta_ip=0.5)
+    assert np.abs(Rr - R).max() < 1e-13 * np.abs(R).max()
+    nelc = (4, 3, 4)
+    Xg = W.mesh_nodes(nelc, *BOX, q=2, displacement=W.periodic_wave_displacement(0.15))
+    u = np.random.Generator(np.random.PCG64(3)).normal(size=(int(np.prod(nelc)), p + 1, p + 1, p + 1))
+    Rc = C.rhs(u, nelc, Xg, p, scheme, eta_ip=0.5)
+    _, detJ = C.metrics(Xg, p)
+    _, w = W.gl_nodes(p + 1)
+    wq = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    assert abs(np.sum(wq * detJ * Rc)) < 1e-14 * np.sum(wq * detJ * np.abs(Rc))
+    assert np.abs(Rc - C.rhs(u, nelc, Xg, p, scheme)).max() > 1e-2 * np.abs(Rc).max()
+    # constants stay at rest: the penalty sees no jump
+    assert np.abs(C.rhs(np.ones_like(u), nelc, Xg, p, scheme, eta_ip=0.5)).max() < 1e-10
