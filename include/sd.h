@@ -175,9 +175,12 @@ int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
  * per element) and from then on sd_rhs and sd_rk_step use them.  Constants
  * are preserved exactly when 2q <= p + 1.  Returns SD_EINVAL for a null
  * argument, q outside {1, 2} or an element whose det J is not positive at
- * a solution point; SD_EUNSUPPORTED for other physics, dimensions or
- * precisions, or with the interior penalty on; SD_ENOMEM / SD_EHIP on
- * device failures.  Calling it again replaces the geometry. */
+ * a solution point (or, with the interior penalty on, at a face point);
+ * SD_EUNSUPPORTED for other physics, dimensions or precisions; SD_ENOMEM /
+ * SD_EHIP on device failures.  With eta_ip > 0 the penalty uses, at each
+ * face point, 1/h = |S_d| max(J^-1 of the two sides) / 2 (on an affine
+ * Cartesian element the 2/h_d of the box) and acts along n = S_d / |S_d|.
+ * Calling it again replaces the geometry. */
 int sd_set_geometry(sd_ctx *ctx, const double *nodes, int q);
 
 /* Timing of the right-hand side kernels: with enable = 1 every later RHS

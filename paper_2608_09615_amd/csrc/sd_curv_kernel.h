@@ -17,7 +17,9 @@
 //                solution keeps the own trace at the other face, which adds
 //                J^-1 M[:, end] (T - u_hat) S_dm to v_m along the lines) or
 //                standard (BR1);
-//   k_cv_rhs     common gradient at the faces (average of the two sides),
+//   k_cv_rhs     common gradient at the faces (average of the two sides,
+//                plus the interior penalty when on: tau (u_R - u_L) along
+//                n = S_d / |S_d|, stored as P = tau / |S_d| per face point),
 //                v_m at the interior flux points, G_d = -nu sum_m S_dm v_m
 //                and du/dt = -J^-1 sum_d D_d G_d.
 #pragma once
@@ -154,6 +156,7 @@ template <int N>
 __global__ void __launch_bounds__(cv_threads<N>()) k_cv_rhs(const double *__restrict__ VF, const double *__restrict__ VS,
                                                        const double *__restrict__ Sf, const double *__restrict__ Jinv,
                                                        const double *__restrict__ ops, KArgs a,
+                                                       const double *__restrict__ T, const double *__restrict__ Pen,
                                                        double *__restrict__ dudt) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF;
@@ -166,9 +169,18 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_rhs(const double *__rest
   for (int t = tid; t < 3 * NP; t += blockDim.x) sV[t] = VS[e * 3 * NP + t];
   for (int t = tid; t < 6 * 3 * NF; t += blockDim.x) {
     const int f = t / (3 * NF), w = t % (3 * NF), d = f >> 1, s = f & 1;
+    const long long en = nbr(a, e, d, s);
     const double own = VF[(e * 6 + f) * 3 * NF + w];
-    const double oth = VF[(nbr(a, e, d, s) * 6 + 2 * d + 1 - s) * 3 * NF + w];
-    sVh[t] = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+    const double oth = VF[(en * 6 + 2 * d + 1 - s) * 3 * NF + w];
+    double vh = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+    if (Pen) {
+      // interior penalty: P (u_R - u_L) S_dm, u_R on the +xi_d side
+      const int m = w / NF, q = w % NF;
+      const double to = T[(e * 6 + f) * NF + q], tn = T[(en * 6 + 2 * d + 1 - s) * NF + q];
+      vh += Pen[(e * 6 + f) * NF + q] * (s == 0 ? to - tn : tn - to) *
+            S[((d * NF + q) * (N + 1) + (s ? N : 0)) * 3 + m];
+    }
+    sVh[t] = vh;
   }
   __syncthreads();
   // G_d = -nu S_d . v at the flux points of family d

@@ -1,7 +1,7 @@
 """Curvilinear hexahedra on the GPU (3-D diffusion, FP64) against the
 curvilinear reference: right-hand sides on affine, rotated (full S) and
-curved meshes, ragged element counts, p = 1..6, both schemes; RK4 and
-SSP-RK(5,4) steps; argument checks.  Bar: 1e-12 of max|R| (the metric terms
+curved meshes, ragged element counts, p = 1..6, both schemes, with and
+without the interior penalty; RK4 and SSP-RK(5,4) steps; argument checks.  Bar: 1e-12 of max|R| (the metric terms
 are computed independently on both sides, each to a few ulps)."""
 import math
 
@@ -58,6 +58,27 @@ def test_curvilinear_rhs_parity(torch_cuda, scheme, p):
 
 
 @pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_curvilinear_interior_penalty_parity(torch_cuda, scheme, p):
+    """Interior penalty on curvilinear elements (tau from |S_d| and the
+    larger J^-1 of the two sides at each face point, along n = S_d/|S_d|)
+    against the reference, on the affine, rotated and curved meshes."""
+    for nel in ((3, 2, 4), (1, 3, 2)):
+        E, n = int(np.prod(nel)), p + 1
+        u = np.random.Generator(np.random.PCG64(7 * p + E)).normal(size=(E, n, n, n))
+        for name, Xg in meshes(nel).items():
+            sd = make(torch_cuda, nel, p, scheme, Xg, eta_ip=0.4)
+            R = sd.rhs(torch_cuda.from_numpy(u[:, None]).to("cuda")).cpu().numpy()[:, 0]
+            sd.close()
+            Ro = C.rhs(u, nel, Xg, p, scheme, nu=0.7, eta_ip=0.4)
+            R0 = C.rhs(u, nel, Xg, p, scheme, nu=0.7)
+            err = np.abs(R - Ro).max() / np.abs(Ro).max()
+            print(f"  ip {name} {nel}: {err:.2e}")
+            assert err < 1e-12, (name, nel, err)
+            assert np.abs(Ro - R0).max() > 1e-3 * np.abs(Ro).max()
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
 def test_curvilinear_16cubed(torch_cuda, scheme):
     """16^3 degree-2 elements at p = 3 (262 144 solution points), every value."""
     nel, p = (16, 16, 16), 3
@@ -110,8 +131,7 @@ def test_curvilinear_argument_checks(torch_cuda):
     nel, p = (2, 2, 2), 2
     good = W.mesh_nodes(nel, *BOX, q=1)
     lo, hi = W.tgv_domain()
-    for kw in (dict(physics="ns", lo=lo, hi=hi), dict(physics="diffusion", precision="fp32", lo=lo, hi=hi),
-               dict(physics="diffusion", eta_ip=0.1, lo=lo, hi=hi)):
+    for kw in (dict(physics="ns", lo=lo, hi=hi), dict(physics="diffusion", precision="fp32", lo=lo, hi=hi)):
         sd = SD(nel, p, scheme="compact", **kw)
         with pytest.raises(SDError):
             sd.set_geometry(good)
