@@ -95,19 +95,20 @@ def test_curvilinear_16cubed(torch_cuda, scheme):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("eta_ip", [0.0, 0.4])
 @pytest.mark.parametrize("integrator", ["rk4", "ssprk54"])
-def test_curvilinear_time_steps(torch_cuda, integrator):
+def test_curvilinear_time_steps(torch_cuda, integrator, eta_ip):
     nel, p, dt, nu = (3, 3, 2), 3, 2e-3, 0.7
     Xg = meshes(nel)["curved"]
     n = p + 1
     u0 = np.random.Generator(np.random.PCG64(12)).normal(size=(int(np.prod(nel)), n, n, n))
-    sd = make(torch_cuda, nel, p, "compact", Xg, nu=nu, integrator=integrator)
+    sd = make(torch_cuda, nel, p, "compact", Xg, nu=nu, integrator=integrator, eta_ip=eta_ip)
     u = torch_cuda.from_numpy(u0[:, None].copy()).to("cuda")
     for _ in range(2):
         sd.rk_step(u, dt)
     got = u.cpu().numpy()[:, 0]
     sd.close()
-    f = lambda v: C.rhs(v, nel, Xg, p, "compact", nu=nu)
+    f = lambda v: C.rhs(v, nel, Xg, p, "compact", nu=nu, eta_ip=eta_ip)
     if integrator == "ssprk54":
         ref = ssprk.integrate(f, u0, dt, 2)
     else:
