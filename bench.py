@@ -79,6 +79,10 @@ TRAFFIC_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispat
 CURV_TRAFFIC_SOURCES = ["sd_curv_kernel.h", "sd_curv.inc", "sd_internal.h", "sd_operators.cpp"]
 
 
+# the sources of k_closure_fused and its launch
+CLOSURE_TRAFFIC_SOURCES = ["sd_closure.inc", "sd_mlp.h", "sd_internal.h"]
+
+
 def sources_sha256(names=None):
     import hashlib
     from paper_2608_09615_amd.build import HIPCC_FLAGS
@@ -336,9 +340,24 @@ def closure_bench(torch, args, p=3, hidden=128, reps=200):
             "us_per_rhs": us[False], "us_per_rhs_with_closure": us[True], "closure_us": extra,
             "closure_tflops": flop / (extra * 1e-6) / 1e12, "rejected_elements": rejected,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernels": "k_closure_fused",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": closure_traffic(N, p, hidden),
+                         "traffic_unit": "B per launch", "algorithmic_bytes": nbytes, "kernels": "k_closure_fused",
                          "mfma_frac_bf16": flop / (extra * 1e-6) / 1e12 / PEAK_BF16_TFLOPS,
                          "duration": "closure_us (RHS time with the closure minus without)"}}
+
+
+def closure_traffic(N, p, hidden):
+    """HBM bytes per k_closure_fused launch from the committed counter
+    record, or None for another workload or once a source it is keyed to
+    has changed."""
+    path = os.path.join(ROOT, "profiles", "closure_traffic_16cubed_p3.json")
+    if not (N == 16 and p == 3 and hidden == 128 and os.path.exists(path)):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if sources_sha256(CLOSURE_TRAFFIC_SOURCES) != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def curv_traffic(N, p, scheme):
