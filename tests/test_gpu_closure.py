@@ -103,13 +103,14 @@ def test_filter_matches_reference(torch_cuda, ratio, p, nelc):
     assert np.abs(Uc - Uo).max() < 1e-13 * np.abs(Uo).max()
 
 
-@pytest.mark.parametrize("n_h,nel", [(32, (3, 2, 2)), (128, (5, 2, 2)), (256, (3, 3, 2))])
+@pytest.mark.parametrize("n_h,nel", [(32, (3, 2, 2)), (128, (5, 2, 2)), (256, (3, 3, 2)), (48, (3, 2, 2))])
 def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
     """R_closure = R_plain + out_scale * net(normalised u) per element; a
     correction larger than max_ratio R is discarded for that element, and
     max_ratio = 0 keeps every finite correction.  12 and 20 elements: one
     padded block, and a full block plus a ragged one, of the single-launch
-    kernel; 256 hidden units take the layer-by-layer path."""
+    kernel (256 hidden units: its variant that reads the later layers'
+    weights layer by layer); 48 hidden units take the layer-by-layer path."""
     print(f"[closure in solver] n_h={n_h} nel={nel}", flush=True)
     torch = torch_cuda
     from paper_2608_09615_amd import SD
@@ -148,7 +149,7 @@ def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
         sd.close()
 
 
-@pytest.mark.parametrize("n_h", [128, 256])
+@pytest.mark.parametrize("n_h", [128, 256, 48])
 def test_closure_rk_step_matches_stage_sequence(torch_cuda, n_h):
     """sd_rk_step with a closure applies each RK4 stage in the closure's
     epilogue (the stage state updated in place): it matches the classical
