@@ -175,6 +175,27 @@ def perturbed_tgv_state(nel, p, seed, amp=1e-2, Ma=0.1, gamma=1.4, noise=0.0, km
     return U
 
 
+def transonic_jet_state(nel, p, peak_mach=1.3, width=0.8, Ma=0.1, gamma=1.4, seed=0):
+    """TGV state with a jet along each axis added to the velocity: a Gaussian
+    profile of peak ``peak_mach`` times the sound speed of the mean state, of
+    half-width ``width`` around a seeded line through the box.  Along the
+    profile the normal velocity passes the sound speed, so faces with a
+    near-sonic Roe average (u_n -+ c close to zero) occur in every direction."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = tgv_domain()
+    X, Y, Z = points_3d(nel, lo, hi, p)
+    rho, u, v, w, pr = tgv_primitive(X, Y, Z, Ma, gamma)
+    c0 = math.sqrt(gamma * pr.mean() / rho.mean())
+    C = rng.uniform(2.0, 4.3, (3, 2))
+    vel = [u, v, w]
+    axes = [(Y, Z), (X, Z), (X, Y)]
+    for d in range(3):
+        A, B = axes[d]
+        r2 = (A - C[d, 0]) ** 2 + (B - C[d, 1]) ** 2
+        vel[d] = vel[d] + (1.0 if d != 1 else -1.0) * peak_mach * c0 * np.exp(-r2 / width ** 2)
+    return conservative(rho, *vel, pr, gamma)
+
+
 def sine_3d(nel, lo, hi, p, k=(1, 1, 1)):
     X, Y, Z = points_3d(nel, lo, hi, p)
     return (np.sin(k[0] * X) * np.sin(k[1] * Y) * np.sin(k[2] * Z))[:, None]

@@ -149,6 +149,39 @@ def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
         sd.close()
 
 
+def test_closure_rearm_with_larger_network(torch_cuda):
+    """One context armed first with a small network and then with larger
+    ones on the layer-by-layer path (48 -> 288 -> 96 hidden units): each RHS
+    equals the one of a fresh context armed once with the same network, so
+    the activation workspace follows the largest shape armed so far."""
+    print("[closure re-arm] 48 -> 288 -> 96", flush=True)
+    torch = torch_cuda
+    from paper_2608_09615_amd import SD
+    p, nel = 3, (3, 2, 2)
+    lo, hi = W.tgv_domain()
+    U = W.perturbed_tgv_state(nel, p, seed=12, noise=1e-3)
+    u = torch.from_numpy(U).to("cuda")
+    nve = 5 * 64
+    shift = [1.0, 0.0, 0.0, 0.0, 178.57]
+    scale = [0.01, 0.5, 0.5, 0.5, 0.2]
+    nets = [make_net(torch, nve, n_h, nve, seed=20 + n_h, bias=0.0)[0] for n_h in (48, 288, 96)]
+    sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+    for net in nets:
+        sd.closure_set(net, shift, scale, [1e-3] * 5, max_ratio=0.0)
+        R = sd.rhs(u).cpu().numpy()
+        fresh = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+        fresh.closure_set(net, shift, scale, [1e-3] * 5, max_ratio=0.0)
+        Rf = fresh.rhs(u).cpu().numpy()
+        fresh.close()
+        assert np.array_equal(R, Rf)
+    sd.closure_set(None)
+    R0 = sd.rhs(u).cpu().numpy()
+    plain = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi)
+    assert np.array_equal(R0, plain.rhs(u).cpu().numpy())
+    plain.close()
+    sd.close()
+
+
 @pytest.mark.parametrize("n_h", [128, 256, 48])
 def test_closure_rk_step_matches_stage_sequence(torch_cuda, n_h):
     """sd_rk_step with a closure applies each RK4 stage in the closure's

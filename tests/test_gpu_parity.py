@@ -134,6 +134,29 @@ def test_3d_ns_parity_bf16x3(torch_cuda, oracle_lib, scheme, p):
     assert err < BF16X3_TOL_NS
 
 
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_ns_entropy_fix_branch_parity(torch_cuda, oracle_lib, scheme, p):
+    """Faces where Harten's fix acts (section 4.4, Roe flux with entropy fix):
+    a TGV state with transonic jets along the three axes.  The oracle's RHS
+    with the fix differs from the one without it by far more than the bar,
+    so the branch is taken; the GPU matches the oracle with the fix."""
+    prm = oracle_lib.make_params("ns", Re=400.0)
+    prm_off = oracle_lib.make_params("ns", Re=400.0, entropy_fix=0.0)
+    lo, hi = W.tgv_domain()
+    nel = (4, 3, 5)
+    U = W.transonic_jet_state(nel, p, seed=p)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+    Roff = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm_off)
+    assert relerr(Roff, Ro) > 1e-5
+    R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp64", lo, hi, Re=400.0)
+    err = relerr(R, Ro)
+    print(f"entropy-fix faces, NS p={p} {scheme}: FP64 {err:.2e} (fix changes the RHS by {relerr(Roff, Ro):.1e})")
+    assert err < FP64_TOL
+    R32, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp32", lo, hi, Re=400.0)
+    assert relerr(R32, Ro) < FP32_TOL_NS
+
+
 def test_ns_p7_runs_in_fp32_only(torch_cuda):
     """p = 7 needs one element's 24 480 LDS values per block: 98 KB in FP32
     and BF16x3, 191 KB in FP64, beyond the 160 KB of a compute unit."""

@@ -102,3 +102,178 @@ def test_sutherland_law(oracle_lib):
         F = oracle_lib.ns_flux_visc(prm, U, G, 1)
         mu = 1e-3 * fac ** 1.5 * (1 + S) / (fac + S)
         assert abs(F[1] - mu) < 1e-15
+
+
+# --- Harten's entropy fix of the interface Roe flux (section 4.4; reading:
+# |lambda| -> (lambda^2 + delta^2) / (2 delta) on the two acoustic waves when
+# |lambda| < delta, delta = 0.1 (|u~_n| + c~) at the Roe state) -------------
+
+def _euler_flux(U, d, gamma=1.4):
+    """Convective flux along e_d; works on complex states (complex step)."""
+    rho = U[0]
+    u = U[1:4] / rho
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * (u @ u))
+    F = np.empty(5, dtype=U.dtype)
+    F[0] = U[1 + d]
+    F[1:4] = U[1:4] * u[d]
+    F[1 + d] += p
+    F[4] = (U[4] + p) * u[d]
+    return F
+
+
+def _jacobian(U, d):
+    """dF_d/dU by complex-step differentiation (exact to rounding)."""
+    h = 1e-30
+    A = np.empty((5, 5))
+    for k in range(5):
+        Z = U.astype(complex)
+        Z[k] += 1j * h
+        A[:, k] = _euler_flux(Z, d).imag / h
+    return A
+
+
+def _roe_state(UL, UR, gamma=1.4):
+    """Conservative state whose u and H are the square-root-density averages
+    (the Euler Jacobian depends on u and H only)."""
+    def uh(U):
+        u = U[1:4] / U[0]
+        p = (gamma - 1.0) * (U[4] - 0.5 * U[0] * (u @ u))
+        return u, (U[4] + p) / U[0]
+    (uL, HL), (uR, HR) = uh(UL), uh(UR)
+    sL, sR = math.sqrt(UL[0]), math.sqrt(UR[0])
+    u = (sL * uL + sR * uR) / (sL + sR)
+    H = (sL * HL + sR * HR) / (sL + sR)
+    E = (H + 0.5 * (gamma - 1.0) * (u @ u)) / gamma
+    return np.array([1.0, *u, E])
+
+
+def _fixed_abs(lam, delta):
+    a = abs(lam)
+    return (a * a + delta * delta) / (2.0 * delta) if a < delta else a
+
+
+def _roe_flux_spectral(UL, UR, d, efix=0.1, fix_waves=(0, 2), delta_scale=1.0):
+    """(F(UL) + F(UR))/2 - f(A~)(UR - UL)/2 with f(A~) evaluated as a matrix
+    function of the Roe-averaged Jacobian: A~ is diagonalisable with the three
+    distinct eigenvalues u_n - c, u_n, u_n + c, so f(A~) is the quadratic
+    Lagrange interpolant of f on them, evaluated at A~ (no eigenvectors)."""
+    A = _jacobian(_roe_state(UL, UR), d)
+    ev = np.sort(np.linalg.eigvals(A).real)
+    lam = [ev[0], ev[2], ev[4]]                 # u_n - c, u_n, u_n + c
+    un, c = lam[1], 0.5 * (lam[2] - lam[0])
+    delta = delta_scale * efix * (abs(un) + c)
+    f = [_fixed_abs(l, delta) if k in fix_waves else abs(l) for k, l in enumerate(lam)]
+    I = np.eye(5)
+    fA = np.zeros((5, 5))
+    for k in range(3):
+        P = I.copy()
+        for j in range(3):
+            if j != k:
+                P = P @ (A - lam[j] * I) / (lam[k] - lam[j])
+        fA += f[k] * P
+    dU = UR - UL
+    return 0.5 * (_euler_flux(UL, d) + _euler_flux(UR, d)) - 0.5 * fA @ dU, A, lam, delta
+
+
+def _near_sonic_pairs():
+    """Face state pairs whose Roe-averaged u_n -+ c lies inside (-delta, delta):
+    transonic jets along +d (u_n ~ c) and along -d (u_n ~ -c)."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    pairs = []
+    for sgn in (1.0, -1.0):
+        for _ in range(6):
+            rho_l, rho_r = rng.uniform(0.8, 1.2, 2)
+            p_l, p_r = rng.uniform(0.6, 0.8, 2)
+            c_l = math.sqrt(1.4 * p_l / rho_l)
+            ul = rng.uniform(-0.2, 0.2, 3)
+            ur = rng.uniform(-0.2, 0.2, 3)
+            pairs.append((sgn, cons(rho_l, ul, p_l), cons(rho_r, ur, p_r), c_l, rng.uniform(0.97, 1.05)))
+    return pairs
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_roe_entropy_fix_against_matrix_function(oracle_lib, d):
+    """Near-sonic faces: the oracle's Roe flux equals the flux built from the
+    Roe-averaged Jacobian with Harten's fix on the acoustic eigenvalues; the
+    Jacobian satisfies the Roe property A~ (UR - UL) = F(UR) - F(UL)."""
+    prm = oracle_lib.make_params("ns")
+    active = 0
+    for sgn, UL, UR, c_l, mach in _near_sonic_pairs():
+        # put the normal velocity of both states near sgn * c
+        for U in (UL, UR):
+            rho = U[0]
+            u = U[1:4] / rho
+            p = 0.4 * (U[4] - 0.5 * rho * (u @ u))
+            u[d] = sgn * mach * c_l
+            U[:] = cons(rho, u, p)
+        Fs, A, lam, delta = _roe_flux_spectral(UL, UR, d)
+        jump = _euler_flux(UR, d) - _euler_flux(UL, d)
+        assert np.abs(A @ (UR - UL) - jump).max() < 1e-12 * np.abs(jump).max()
+        acoustic = lam[0] if sgn > 0 else lam[2]
+        assert abs(acoustic) < delta              # the fixed branch is the one taken
+        active += 1
+        F = oracle_lib.ns_roe(prm, UL, UR, d)
+        scale = np.abs(F).max()
+        assert np.abs(F - Fs).max() < 2e-13 * scale, (d, sgn)
+    assert active == 12
+
+
+def _low_mach_pairs(d):
+    """Face state pairs of the Ma = 0.1 Taylor-Green regime: |u_n| < delta, so
+    a fix wrongly applied to the contact wave would act."""
+    rng = np.random.Generator(np.random.PCG64(77 + d))
+    out = []
+    for _ in range(8):
+        UL = cons(rng.uniform(0.9, 1.1), rng.uniform(-1, 1, 3), rng.uniform(70, 73))
+        UR = cons(rng.uniform(0.9, 1.1), rng.uniform(-1, 1, 3), rng.uniform(70, 73))
+        out.append((UL, UR))
+    return out
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_roe_low_mach_against_matrix_function(oracle_lib, d):
+    """Low-Mach faces (the Taylor-Green regime): acoustic waves far above
+    delta, contact wave below it and left unfixed."""
+    prm = oracle_lib.make_params("ns")
+    for UL, UR in _low_mach_pairs(d):
+        Fs, A, lam, delta = _roe_flux_spectral(UL, UR, d)
+        assert abs(lam[1]) < delta < min(abs(lam[0]), abs(lam[2]))
+        F = oracle_lib.ns_roe(prm, UL, UR, d)
+        assert np.abs(F - Fs).max() < 2e-13 * np.abs(F).max()
+
+
+def test_roe_entropy_fix_detects_planted_slips(oracle_lib):
+    """The matrix-function construction tells the fix apart from plausible
+    slips: delta doubled or no fix (near-sonic faces), the fix also applied
+    to the contact wave u_n (low-Mach faces).  Each slip moves the flux far
+    beyond the parity tolerance."""
+    prm = oracle_lib.make_params("ns")
+    d = 0
+    worst = {"delta x2": np.inf, "no fix": np.inf, "fix on u_n": np.inf}
+    for sgn, UL, UR, c_l, mach in _near_sonic_pairs():
+        for U in (UL, UR):
+            rho = U[0]
+            u = U[1:4] / rho
+            p = 0.4 * (U[4] - 0.5 * rho * (u @ u))
+            u[d] = sgn * mach * c_l
+            U[:] = cons(rho, u, p)
+        F = oracle_lib.ns_roe(prm, UL, UR, d)
+        scale = np.abs(F).max()
+        for k, kw in (("delta x2", dict(delta_scale=2.0)), ("no fix", dict(fix_waves=()))):
+            worst[k] = min(worst[k], np.abs(F - _roe_flux_spectral(UL, UR, d, **kw)[0]).max() / scale)
+    for UL, UR in _low_mach_pairs(d):
+        F = oracle_lib.ns_roe(prm, UL, UR, d)
+        Fk = _roe_flux_spectral(UL, UR, d, fix_waves=(0, 1, 2))[0]
+        worst["fix on u_n"] = min(worst["fix on u_n"], np.abs(F - Fk).max() / np.abs(F).max())
+    for k, v in worst.items():
+        assert v > 1e-6, (k, v)
+
+
+def test_entropy_fix_is_continuous_at_delta():
+    """The fixed eigenvalue meets |lambda| at |lambda| = delta and stays at or
+    above delta / 2 (its value at lambda = 0)."""
+    for delta in (0.05, 0.3, 2.0):
+        assert abs(_fixed_abs(delta * (1 - 1e-12), delta) - delta) < 1e-11 * delta
+        assert _fixed_abs(0.0, delta) == pytest.approx(0.5 * delta, rel=1e-15)
+        for l in np.linspace(-delta, delta, 11):
+            assert _fixed_abs(l, delta) >= abs(l)
