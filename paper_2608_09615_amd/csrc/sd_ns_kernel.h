@@ -38,20 +38,12 @@ namespace sd {
 
 constexpr int kNsMaxEpb = 8;
 
-// Largest block of k_rhs_ns: 512 threads where the face pass fits in 128
-// VGPR-pairs' worth of registers per lane, 256 where FP64 at n >= 5 needs
-// the whole register file of a lane (one wavefront per SIMD).
+// Largest block of k_rhs_ns (four wavefronts).
 template <int N, typename R>
 __host__ __device__ constexpr int ns_max_threads() {
-  return (sizeof(R) == 8 && N >= 5) ? 256 : 512;
+  return 256;
 }
 
-#ifndef SD_NS_SMEM_TARGET
-#define SD_NS_SMEM_TARGET (64 * 1024)
-#endif
-#ifndef SD_NS_THREADS_PER_ELEM
-#define SD_NS_THREADS_PER_ELEM 0
-#endif
 
 template <int N, typename R>
 struct NsOps {
@@ -62,6 +54,7 @@ struct NsOps {
   R Mc[2][N];
   R rrow[2][N];
   R kap[2];
+  R kapx[2];    // (L M)[end_s][end_other]: BR1's opposite-face term
   // auxiliary gradient along a line regrouped by linearity:
   // D u + Mc0 (uh0 - Lend0 u) + Mc1 (uh1 - Lend1 u) with uh = (t + Lend u)/2
   // = A u + hMc0 t0 + hMc1 t1, A = D - (Mc0 Lend0^T + Mc1 Lend1^T)/2
@@ -169,25 +162,22 @@ struct NsSmem {
 
 // Launch shape of k_rhs_ns, fixed per instantiation so that the work-item
 // index arithmetic divides by compile-time constants: as many elements per
-// block as fit the LDS target (at most one full block of solution points and
-// kNsMaxEpb), and ns_lanes threads per element, capped by the launch bound
-// (512 for four FP32 p = 3 elements, 256 for two FP64 ones).
+// block as fit a 64 KB LDS target (at most one full block of solution points
+// and kNsMaxEpb), and ns_lanes threads per element, at most 256 per block.
+// Work items are ordered face-major (P3), direction-major (P2, P4, P5), so
+// that with epb * n^2 = 64 (p = 3: four elements) every wavefront works on a
+// single face or direction and runs one specialised body.
 template <int N, typename R>
 __host__ __device__ constexpr int ns_epb() {
-#ifdef SD_NS_EPB
-  if (SD_NS_EPB > 0) return SD_NS_EPB;
-#endif
   constexpr long long per = (long long)NsSmem<N>::TOTAL * (long long)sizeof(R);
-  long long e = (long long)(SD_NS_SMEM_TARGET) / per;
+  long long e = (64LL * 1024) / per;
   const long long cap = (256 / (N * N * N)) > 1 ? (256 / (N * N * N)) : 1;
   if (e > cap) e = cap;
   if (e > kNsMaxEpb) e = kNsMaxEpb;
   return e < 1 ? 1 : (int)e;
 }
 // Lanes per element, measured per degree and precision (TGV workloads of
-// 1.9-17 M solution points): the block's elements are fixed by the LDS, and
-// the lanes decide how its wavefronts pack next to the VGPR limit, which is
-// not monotone (n = 4: 128 beats 64 by 5-9%; n = 5: 200 loses 45% to 100).
+// 1.9-17 M solution points).
 template <int N, typename R>
 __host__ __device__ constexpr int ns_lanes() {
   constexpr bool f64 = sizeof(R) == 8;
@@ -195,9 +185,25 @@ __host__ __device__ constexpr int ns_lanes() {
 }
 template <int N, typename R>
 __host__ __device__ constexpr int ns_threads() {
-  const int tpe = (SD_NS_THREADS_PER_ELEM) > 0 ? (SD_NS_THREADS_PER_ELEM) : ns_lanes<N, R>();
-  const int t = (ns_epb<N, R>() * tpe + 63) / 64 * 64;
+  const int t = (ns_epb<N, R>() * ns_lanes<N, R>() + 63) / 64 * 64;
   return t < ns_max_threads<N, R>() ? t : ns_max_threads<N, R>();
+}
+
+// Number of neighbours whose state an element reads: 6 across the faces and
+// 12 across the edges; BR1 adds the 6 at distance two along the axes (the
+// common solution at a face neighbour's far face enters its standard normal
+// gradient).
+template <bool COMPACT>
+__host__ __device__ constexpr int ns_nnb() { return COMPACT ? 18 : 24; }
+
+// Element of block b: blocks are dealt to the eight XCDs of the chip in turn
+// (b % 8), so each XCD is given a contiguous range of elements and walks it
+// in order; the neighbours an element reads were then read shortly before by
+// blocks of the same XCD and are found in its L2.
+__device__ __forceinline__ long long ns_block_elem(long long b, long long nblocks, int epb) {
+  const long long q = nblocks / 8, r = nblocks % 8;
+  const long long x = b % 8, k = b / 8;
+  return (x * q + (x < r ? x : r) + k) * epb;
 }
 
 // number of values moved per vector load for a contiguous run of CNT values
@@ -509,29 +515,321 @@ __global__ void __launch_bounds__(256) k_traces_ns(const double *__restrict__ U,
 
 // Chained RK stages (fused path without a closure): the stage state between
 // stages is kept in compute precision with the reference state removed (the
-// value the kernel would round the FP64 state to), and each stage emits the
-// trace records of the next stage's state, so the trace kernel runs once per
-// step.  in_r: stage state to read instead of U (nullptr: U); out_r: where the
-// stage epilogue writes the next stage state (nullptr: FP64 epilogue of
-// RkEpi); xnext: trace records of out_r.
+// value the kernel would round the FP64 state to).  in_r: stage state to
+// read instead of U (nullptr: U); out_r: where the stage epilogue writes the
+// next stage state (nullptr: FP64 epilogue of RkEpi).  Every block reads the
+// states of its elements' neighbours, so out_r must not alias in_r.
 template <typename R>
 struct NsChain {
   const R *in_r;
   R *out_r;
-  R *xnext;
 };
 
+// Readers of the stage state for the prologue of k_rhs_ns: compute-precision
+// stage state (reference already removed), or the FP64 state U with the
+// reference state (U0[0] on rho, U0[4] on rho E; zero on the momenta) removed
+// before rounding.
+template <typename R>
+struct NsSrcR {
+  const R *__restrict__ p;
+  __device__ __forceinline__ R operator()(long long i, int) const { return p[i]; }
+  template <int W>
+  __device__ __forceinline__ void vec(long long i, int, R *x, std::integral_constant<int, W>) const {
+    using V = typename VecT<R, W>::T;
+    const V v = *reinterpret_cast<const V *>(p + i);
+    const R *xv = reinterpret_cast<const R *>(&v);
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = xv[w];
+  }
+};
+template <typename R>
+struct NsSrcU {
+  const double *__restrict__ p;
+  double r0, e0;
+  __device__ __forceinline__ R operator()(long long i, int v) const {
+    return (R)(p[i] - (v == 0 ? r0 : (v == 4 ? e0 : 0.0)));
+  }
+  // W consecutive values of one variable v (W divides the per-variable count)
+  template <int W>
+  __device__ __forceinline__ void vec(long long i, int v, R *x, std::integral_constant<int, W>) const {
+    const double u0 = v == 0 ? r0 : (v == 4 ? e0 : 0.0);
+    if constexpr (W % 2 == 0) {
+#pragma unroll
+      for (int w = 0; w < W; w += 2) {
+        const double2 d = *reinterpret_cast<const double2 *>(p + i + w);
+        x[w] = (R)(d.x - u0);
+        x[w + 1] = (R)(d.y - u0);
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) x[w] = (R)(p[i + w] - u0);
+    }
+  }
+};
+
+// Neighbour k of element e: k < 6 across face (k >> 1, k & 1); 6 <= k < 18
+// across edge k - 6 (a step along lo to side slo and along hi to side shi,
+// the edge numbering of the trace records); 18 <= k < 24 two steps across
+// face k - 18 (BR1 only).  Periodic box.
+__device__ __forceinline__ int ns_neighbour(const KArgs &a, int e, int k) {
+  const int nx = a.nel[0], ny = a.nel[1], nz = a.nel[2];
+  int c[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
+  const int ext[3] = {nx, ny, nz};
+  auto step = [&](int d, int s, int dist) {
+    int x = pick(d, c[0], c[1], c[2]);
+    const int n = pick(d, ext[0], ext[1], ext[2]);
+    x = s ? (x + dist) % n : (x - dist % n + n) % n;
+    if (d == 0) c[0] = x;
+    else if (d == 1) c[1] = x;
+    else c[2] = x;
+  };
+  if (k < 6) {
+    step(k >> 1, k & 1, 1);
+  } else if (k < 18) {
+    const int ed = k - 6, P = ed >> 2;
+    step(P == 2 ? 1 : 0, (ed >> 1) & 1, 1);
+    step(P == 0 ? 1 : 2, ed & 1, 1);
+  } else {
+    step((k - 18) >> 1, (k - 18) & 1, 2);
+  }
+  return c[0] + nx * (c[1] + ny * c[2]);
+}
+
+// Prologue of k_rhs_ns for a block: the state of its elements into LDS, the
+// neighbours' face traces T and normal-gradient traces NN of the shared faces
+// and the edge neighbours' edge traces, computed from the neighbours' states
+// read through the source src (NsSrcR or NsSrcU).  Every global read is
+// unrolled with a compile-time trip count and issued in chunks of about 64
+// registers before any of them is used, so that an element waits for the
+// latency of its neighbour reads once or twice, not once per work item.
+template <int N, typename R>
+struct NsTraceOps {
+  R Lend[2][N];
+  R rrow[2][N];
+  R kapx[2];
+};
+
+template <int N, typename R, bool COMPACT, int NNB, class Src>
+__device__ __forceinline__ void ns_prologue(const Src &src, const NsTraceOps<N, R> op, R *sm,
+                                            const int (*snb)[NNB], int e0, int nb, int tid) {
+  using SM = NsSmem<N>;
+  constexpr int NP = SM::NP, NF = SM::NF;
+  constexpr int nth = ns_threads<N, R>();
+  constexpr int epb = ns_epb<N, R>();
+  // own state into LDS (x-lines at pitch PT)
+  auto own_state = [&]() __attribute__((always_inline)) {
+    constexpr int W = vec_width<R, 5 * NP>();
+    constexpr int RND = (epb * 5 * NP / W + nth - 1) / nth;
+#pragma unroll
+    for (int it = 0; it < RND; ++it) {
+      const int t = tid + it * nth;
+      if (t < nb * 5 * NP / W) {
+        const int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
+        R xv[W];
+        src.vec((long long)e0 * 5 * NP + (long long)t * W, r / NP, xv, std::integral_constant<int, W>{});
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const int rw = r + w;
+          sm[el * SM::TOTAL + SM::U + (rw / NP) * SM::NPP + ns_pidx<N, SM::PT>(rw % NP)] = xv[w];
+        }
+      }
+    }
+  };
+  // face neighbours: T and NN of the shared face.  The directions are
+  // unrolled at compile time, so the reads of a line sit at constant offsets
+  // from one address; work items past the end read valid data of the first
+  // item and store nothing, so the reads need no branches.
+  constexpr int FCNT = epb * 2 * 5 * NF, FRND = (FCNT + nth - 1) / nth;
+  constexpr int NL = COMPACT ? N : 2 * N;
+  struct FaceBuf {
+    R x[FRND][NL];
+  };
+  auto faces_load = [&](auto Dc, FaceBuf &b) __attribute__((always_inline)) {
+    constexpr int D = decltype(Dc)::value;
+    constexpr int ST = D == 0 ? 1 : (D == 1 ? N : N * N);
+#pragma unroll
+    for (int it = 0; it < FRND; ++it) {
+      const int t = tid + it * nth, tc = t < FCNT ? t : 0;
+      const int S = tc / (epb * 5 * NF), r = tc % (epb * 5 * NF), el = r / (5 * NF), w = r % (5 * NF);
+      const int v = w / NF, q = w % NF;
+      int base, stride;
+      ns_line<N, N>(D, q, base, stride);
+      const int elc = el < nb ? el : 0;
+      const long long o = (long long)snb[elc][2 * D + S] * 5 * NP + v * NP + base;
+#pragma unroll
+      for (int c = 0; c < N; ++c) b.x[it][c] = src(o + c * ST, v);
+      if constexpr (!COMPACT) {
+        const long long o2 = (long long)snb[elc][18 + 2 * D + S] * 5 * NP + v * NP + base;
+#pragma unroll
+        for (int c = 0; c < N; ++c) b.x[it][N + c] = src(o2 + c * ST, v);
+      }
+    }
+  };
+  auto faces_compute = [&](auto Dc, const FaceBuf &b) __attribute__((always_inline)) {
+    constexpr int D = decltype(Dc)::value;
+#pragma unroll
+    for (int it = 0; it < FRND; ++it) {
+      const int t = tid + it * nth;
+      const int S = t / (epb * 5 * NF), r = t % (epb * 5 * NF), el = r / (5 * NF), w = r % (5 * NF);
+      const int v = w / NF, q = w % NF;
+      // the neighbour's side of the shared face is 1 - S; the operator rows
+      // stay at compile-time indices (SC: side S known at compile time)
+      auto side = [&](auto SC, R &tr, R &nn) __attribute__((always_inline)) {
+        constexpr int SS = decltype(SC)::value, SO = 1 - SS;
+        tr = R(0);
+        nn = R(0);
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          tr += op.Lend[SO][c] * b.x[it][c];
+          nn += op.rrow[SO][c] * b.x[it][c];
+        }
+        if constexpr (!COMPACT) {
+          // BR1: common solution at the neighbour's far face (side S)
+          R mine = R(0), theirs = R(0);
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            mine += op.Lend[SS][c] * b.x[it][c];
+            theirs += op.Lend[SO][c] * b.x[it][N + c];
+          }
+          const R uh = SS ? R(0.5) * (mine + theirs) : R(0.5) * (theirs + mine);
+          nn += op.kapx[SO] * uh;
+        }
+      };
+      R tr, nn;
+      if constexpr ((epb * 5 * NF) % 64 == 0) {
+        // S is the same across the wavefront: one side's sums
+        if (__builtin_amdgcn_readfirstlane(S)) side(std::integral_constant<int, 1>{}, tr, nn);
+        else side(std::integral_constant<int, 0>{}, tr, nn);
+      } else {
+        // both sides' sums formed, one selected
+        R ta, na, tb, nb2;
+        side(std::integral_constant<int, 1>{}, ta, na);
+        side(std::integral_constant<int, 0>{}, tb, nb2);
+        tr = S ? ta : tb;
+        nn = S ? na : nb2;
+      }
+      if (t < FCNT && el < nb) {
+        R *E = sm + el * SM::TOTAL;
+        const int f = 2 * D + S;
+        E[SM::TNN + (f * 10 + v) * NF + q] = tr;
+        E[SM::TNN + (f * 10 + 5 + v) * NF + q] = nn;
+      }
+    }
+  };
+  // edge neighbours, one edge family P (edges along t3, spanned by lo < hi)
+  // at a time: the trace of the neighbour across edge ed at the shared edge,
+  // i.e. its face trace on face (lo, 1 - slo) interpolated along hi to side
+  // 1 - shi
+  constexpr int ECNT = epb * 4 * 5 * N, ERND = (ECNT + nth - 1) / nth;
+  struct EdgeBuf {
+    R x[ERND][N * N];
+  };
+  auto edges_load = [&](auto Pc, EdgeBuf &b) __attribute__((always_inline)) {
+    constexpr int P = decltype(Pc)::value;
+    constexpr int lo = P == 2 ? 1 : 0, hi = P == 0 ? 1 : 2, t3 = 3 - lo - hi;
+    constexpr int SL = lo == 0 ? 1 : N, SH = hi == 1 ? N : N * N, ST = t3 == 2 ? N * N : (t3 == 1 ? N : 1);
+#pragma unroll
+    for (int it = 0; it < ERND; ++it) {
+      const int t = tid + it * nth, tc = t < ECNT ? t : 0;
+      const int el = tc / (20 * N), r = tc % (20 * N), e4 = r / (5 * N), w = r % (5 * N), v = w / N, at = w % N;
+      const int elc = el < nb ? el : 0;
+      const long long o = (long long)snb[elc][6 + 4 * P + e4] * 5 * NP + v * NP + at * ST;
+#pragma unroll
+      for (int c2 = 0; c2 < N; ++c2)
+#pragma unroll
+        for (int c1 = 0; c1 < N; ++c1) b.x[it][c2 * N + c1] = src(o + c1 * SL + c2 * SH, v);
+    }
+  };
+  auto edges_compute = [&](auto Pc, const EdgeBuf &b) __attribute__((always_inline)) {
+    constexpr int P = decltype(Pc)::value;
+#pragma unroll
+    for (int it = 0; it < ERND; ++it) {
+      const int t = tid + it * nth;
+      const int el = t / (20 * N), r = t % (20 * N), e4 = r / (5 * N), w = r % (5 * N), v = w / N, at = w % N;
+      const bool slo = (e4 >> 1) != 0, shi = (e4 & 1) != 0;
+      // both sides' sums formed, one selected
+      R a0 = R(0), a1 = R(0);
+#pragma unroll
+      for (int c2 = 0; c2 < N; ++c2) {
+        R i0 = R(0), i1 = R(0);
+#pragma unroll
+        for (int c1 = 0; c1 < N; ++c1) {
+          i0 += op.Lend[0][c1] * b.x[it][c2 * N + c1];
+          i1 += op.Lend[1][c1] * b.x[it][c2 * N + c1];
+        }
+        const R inner = slo ? i0 : i1;
+        a0 += op.Lend[0][c2] * inner;
+        a1 += op.Lend[1][c2] * inner;
+      }
+      if (t < ECNT && el < nb) sm[el * SM::TOTAL + SM::E + ((4 * P + e4) * 5 + v) * N + at] = shi ? a0 : a1;
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  // reads issued ahead of the arithmetic that uses them, as far as about 48
+  // registers of read data allow
+  constexpr int FACE_REGS = 3 * FRND * NL * (int)(sizeof(R) / 4);
+  if constexpr (FACE_REGS <= 48) {
+    FaceBuf f0, f1, f2;
+    faces_load(I0{}, f0);
+    faces_load(I1{}, f1);
+    faces_load(I2{}, f2);
+    own_state();
+    faces_compute(I0{}, f0);
+    faces_compute(I1{}, f1);
+    faces_compute(I2{}, f2);
+  } else {
+    own_state();
+    FaceBuf f0;
+    faces_load(I0{}, f0);
+    faces_compute(I0{}, f0);
+    FaceBuf f1;
+    faces_load(I1{}, f1);
+    faces_compute(I1{}, f1);
+    FaceBuf f2;
+    faces_load(I2{}, f2);
+    faces_compute(I2{}, f2);
+  }
+  EdgeBuf g0;
+  edges_load(I0{}, g0);
+  edges_compute(I0{}, g0);
+  EdgeBuf g1;
+  edges_load(I1{}, g1);
+  edges_compute(I1{}, g1);
+  EdgeBuf g2;
+  edges_load(I2{}, g2);
+  edges_compute(I2{}, g2);
+}
+
+// Wavefronts per SIMD that the LDS of k_rhs_ns allows (160 KB per compute
+// unit, four SIMDs): the register budget the kernel is compiled for, so that
+// registers do not limit the occupancy below what the LDS gives (rounded
+// down, except that 1.5 counts as 2).
+template <int N, typename R>
+__host__ __device__ constexpr int ns_waves_per_simd() {
+  const int blocks = (160 * 1024) / ((int)sizeof(R) * NsSmem<N>::TOTAL * ns_epb<N, R>() + 1024);
+  const int tot = blocks * (ns_threads<N, R>() / 64);
+  const int w = (tot >= 6 && tot < 8) ? 2 : tot / 4;
+  // at most four (128 registers or more); FP64 at most two (its values take
+  // register pairs, and the face pass then needs about 250 registers)
+  const int cap = sizeof(R) == 8 ? 2 : 4;
+  return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
 template <int N, typename R, bool COMPACT, bool SPLIT = false>
-__global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const double *__restrict__ U, const R *__restrict__ X,
-                                                double *__restrict__ dudt, KArgs a, NsOps<N, R> op, RkEpi ep,
-                                                NsSplitOps<N> spo, NsChain<R> ch) {
+__global__ void __launch_bounds__((ns_threads<N, R>()))
+__attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(const double *__restrict__ U,
+                                                                 double *__restrict__ dudt, KArgs a,
+                                                                 NsOps<N, R> op, RkEpi ep, NsSplitOps<N> spo,
+                                                                 NsChain<R> ch) {
   static_assert(!SPLIT || sizeof(R) == 4, "BF16x3 works on the FP32 kernel");
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
-  constexpr int XS = trace_stride(3, N, 5), FS = trace_face_stride(3, N, 5), EO = trace_edge_off(3, N, 5);
+  constexpr int NNB = ns_nnb<COMPACT>();
   extern __shared__ double2 smem_ns[];          // 16-byte aligned dynamic LDS
   R *sm = reinterpret_cast<R *>(smem_ns);
-  __shared__ int snb[kNsMaxEpb][18];
+  __shared__ int snb[ns_epb<N, R>()][NNB];
   __shared__ NsSplitOps<SPLIT ? N : 1> ssp;
   constexpr int nth = ns_threads<N, R>();          // == blockDim.x
   const int tid = threadIdx.x;
@@ -541,88 +839,30 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
       reinterpret_cast<uint32_t *>(&ssp)[t] = reinterpret_cast<const uint32_t *>(&spo)[t];
   }
   constexpr int epb = ns_epb<N, R>();              // == a.epb
-  const int e0 = blockIdx.x * epb;
+  const long long nblocks = (a.ne + epb - 1) / epb;
+  const int e0 = (int)ns_block_elem(blockIdx.x, nblocks, epb);
   const int nb = min(epb, (int)(a.ne - e0));
+  const R *__restrict__ in_r = ch.in_r;
 
-  // P0: neighbour table and state
-  for (int t = tid; t < nb * 18; t += nth) {
-    int el = t / 18, k = t % 18;
-    int e = e0 + el;
-    const int nx = a.nel[0], ny = a.nel[1], nz = a.nel[2];
-    int cx = e % nx, cy = (e / nx) % ny, cz = e / (nx * ny);
-    // the one or two steps of neighbour k: (direction, side) pairs
-    int d0, s0, d1 = -1, s1 = 0;
-    if (k < 6) {
-      d0 = k >> 1;
-      s0 = k & 1;
-    } else {
-      int ed = k - 6, P = ed >> 2;
-      d0 = P == 2 ? 1 : 0;
-      s0 = (ed >> 1) & 1;
-      d1 = P == 0 ? 1 : 2;
-      s1 = ed & 1;
-    }
-    auto wrap = [](int c, int s, int ext) { return s ? (c + 1 == ext ? 0 : c + 1) : (c == 0 ? ext - 1 : c - 1); };
-    if (d0 == 0 || d1 == 0) cx = wrap(cx, d0 == 0 ? s0 : s1, nx);
-    if (d0 == 1 || d1 == 1) cy = wrap(cy, d0 == 1 ? s0 : s1, ny);
-    if (d0 == 2 || d1 == 2) cz = wrap(cz, d0 == 2 ? s0 : s1, nz);
-    snb[el][k] = cx + nx * (cy + ny * cz);
-  }
-  if (ch.in_r) {
-    // stage state already in compute precision, reference removed
-    constexpr int W = vec_width<R, 5 * NP>();
-    using V = typename VecT<R, W>::T;
-    const V *src = reinterpret_cast<const V *>(ch.in_r + (long long)e0 * 5 * NP);
-    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
-      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
-      const V x = src[t];
-      const R *xv = reinterpret_cast<const R *>(&x);
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int rw = r + w;
-        sm[el * SM::TOTAL + SM::U + (rw / NP) * SM::NPP + ns_pidx<N, SM::PT>(rw % NP)] = xv[w];
-      }
-    }
-  } else {
-    constexpr int W = (NP % 2 == 0) ? 2 : 1;
-    using V = typename VecT<double, W>::T;
-    const V *src = reinterpret_cast<const V *>(U + (long long)e0 * 5 * NP);
-    for (int t = tid; t < nb * 5 * NP / W; t += nth) {
-      int r = (t * W) % (5 * NP), el = (t * W) / (5 * NP);
-      double u0 = a.U0[r / NP];
-      R *dst = sm + el * SM::TOTAL + SM::U + (r / NP) * SM::NPP;
-      if constexpr (W == 2) {
-        V x = src[t];
-        dst[ns_pidx<N, SM::PT>(r % NP)] = (R)(x.x - u0);
-        dst[ns_pidx<N, SM::PT>(r % NP + 1)] = (R)(x.y - u0);
-      } else {
-        dst[ns_pidx<N, SM::PT>(r % NP)] = (R)(src[t] - u0);
-      }
-    }
-  }
+  // P0: neighbour table; then the state and the neighbours' traces computed
+  // from their states (read through L2)
+  for (int t = tid; t < nb * NNB; t += nth) snb[t / NNB][t % NNB] = ns_neighbour(a, e0 + t / NNB, t % NNB);
   __syncthreads();
-  // neighbour traces (T and NN of the shared face) and edge traces
   {
-    constexpr int CNT = 10 * NF, W = vec_width<R, CNT>();
-    using V = typename VecT<R, W>::T;
-    for (int t = tid; t < nb * 6 * CNT / W; t += nth) {
-      int el = t / (6 * CNT / W), r = t % (6 * CNT / W);
-      int f = r / (CNT / W), w = r % (CNT / W);
-      int d = f >> 1, s = f & 1;
-      const V *src = reinterpret_cast<const V *>(X + (long long)snb[el][f] * XS + (2 * d + 1 - s) * FS);
-      reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::TNN + f * CNT)[w] = src[w];
+    // the operator rows of the prologue, copied with compile-time indices
+    // (each of the two inlined prologues then keeps them in registers)
+    NsTraceOps<N, R> to;
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        to.Lend[s2][c] = op.Lend[s2][c];
+        to.rrow[s2][c] = op.rrow[s2][c];
+      }
+      to.kapx[s2] = op.kapx[s2];
     }
-  }
-  {
-    constexpr int CNT = 5 * N, W = vec_width<R, CNT>();
-    using V = typename VecT<R, W>::T;
-    for (int t = tid; t < nb * 12 * CNT / W; t += nth) {
-      int el = t / (12 * CNT / W), r = t % (12 * CNT / W);
-      int ed = r / (CNT / W), w = r % (CNT / W);
-      int opp = (ed & ~3) + 2 * (1 - ((ed >> 1) & 1)) + (1 - (ed & 1));
-      const V *src = reinterpret_cast<const V *>(X + (long long)snb[el][6 + ed] * XS + EO + opp * CNT);
-      reinterpret_cast<V *>(sm + el * SM::TOTAL + SM::E + ed * CNT)[w] = src[w];
-    }
+    if (in_r) ns_prologue<N, R, COMPACT, NNB>(NsSrcR<R>{in_r}, to, sm, snb, e0, nb, tid);
+    else ns_prologue<N, R, COMPACT, NNB>(NsSrcU<R>{U, a.U0[0], a.U0[4]}, to, sm, snb, e0, nb, tid);
   }
   __syncthreads();
   // P2: gradient at the solution points
@@ -689,27 +929,43 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     }
   }
   __syncthreads();
-  // P3: interface fluxes, face-major work items; the same thread takes the
-  // same face point in both passes, so the second reads its own LDS writes
-  auto p3 = [&](auto Pc) {
+  // P3: interface fluxes, face-major work items, in two passes (minus the
+  // viscous flux, then plus the Roe flux) over the face points
+  auto p3item = [&](auto Pc, int t) {
     constexpr int PART = decltype(Pc)::value;
-    for (int t = tid; t < 6 * epb * NF; t += nth) {
-      int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
-      if (el >= nb) continue;
-      R *E = sm + el * SM::TOTAL;
-      switch (f) {
-        case 0: ns_face_item<N, R, COMPACT, 0, 0, PART>(a, op, E, q); break;
-        case 1: ns_face_item<N, R, COMPACT, 0, 1, PART>(a, op, E, q); break;
-        case 2: ns_face_item<N, R, COMPACT, 1, 0, PART>(a, op, E, q); break;
-        case 3: ns_face_item<N, R, COMPACT, 1, 1, PART>(a, op, E, q); break;
-        case 4: ns_face_item<N, R, COMPACT, 2, 0, PART>(a, op, E, q); break;
-        default: ns_face_item<N, R, COMPACT, 2, 1, PART>(a, op, E, q); break;
-      }
+    const int f = t / (epb * NF), r = t % (epb * NF), el = r / NF, q = r % NF;
+    if (el >= nb) return;
+    R *E = sm + el * SM::TOTAL;
+    switch (f) {
+      case 0: ns_face_item<N, R, COMPACT, 0, 0, PART>(a, op, E, q); break;
+      case 1: ns_face_item<N, R, COMPACT, 0, 1, PART>(a, op, E, q); break;
+      case 2: ns_face_item<N, R, COMPACT, 1, 0, PART>(a, op, E, q); break;
+      case 3: ns_face_item<N, R, COMPACT, 1, 1, PART>(a, op, E, q); break;
+      case 4: ns_face_item<N, R, COMPACT, 2, 0, PART>(a, op, E, q); break;
+      default: ns_face_item<N, R, COMPACT, 2, 1, PART>(a, op, E, q); break;
     }
   };
-  p3(std::integral_constant<int, 0>{});
-  p3(std::integral_constant<int, 1>{});
-  __syncthreads();
+  constexpr int PI = 6 * epb * NF;   // face points of the block: items per pass
+  if constexpr (PI >= nth) {
+    // both passes as one list of 2 PI items in rounds of nth separated by
+    // barriers: a face point's second pass falls in a later round than its
+    // first (PI >= nth), and no wavefront idles while the others finish a
+    // pass (at p = 3, 6 x 64 + 6 x 64 items are three rounds of four
+    // wavefronts, each on one face and pass)
+    constexpr int RND = (2 * PI + nth - 1) / nth;
+    for (int rr = 0; rr < RND; ++rr) {
+      const int t = tid + rr * nth;
+      if (t < PI) p3item(std::integral_constant<int, 0>{}, t);
+      else if (t < 2 * PI) p3item(std::integral_constant<int, 1>{}, t - PI);
+      __syncthreads();
+    }
+  } else {
+    // the same thread takes the same face point in both passes, so the
+    // second reads its own LDS writes
+    for (int t = tid; t < PI; t += nth) p3item(std::integral_constant<int, 0>{}, t);
+    for (int t = tid; t < PI; t += nth) p3item(std::integral_constant<int, 1>{}, t);
+    __syncthreads();
+  }
   // P4: interior fluxes, items ordered (direction, flux point, element, line)
   for (int t = tid; t < 3 * (N - 1) * epb * NF; t += nth) {
     int d = t / ((N - 1) * epb * NF), r0 = t % ((N - 1) * epb * NF);
@@ -723,6 +979,20 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     }
   }
   __syncthreads();
+  // RK stage inputs of this thread's values, requested now so that their
+  // latency passes during the divergence
+  constexpr int ERK = (epb * 5 * NP + nth - 1) / nth;
+  constexpr bool PREF = ERK * 4 <= 24;     // registers of the prefetched values
+  double pu0[ERK], pac[ERK];
+  if (PREF && ep.mode != 0) {
+#pragma unroll
+    for (int k = 0; k < ERK; ++k) {
+      const int t = tid + k * nth;
+      const long long i = (long long)e0 * 5 * NP + (t < nb * 5 * NP ? t : 0);
+      pu0[k] = __builtin_nontemporal_load(ep.u0 + i);
+      pac[k] = ep.first ? 0.0 : __builtin_nontemporal_load(ep.acc + i);
+    }
+  }
   // P5: divergence per line and variable, items ordered (direction, element,
   // variable, line); then the three contributions summed in FP64
   if constexpr (SPLIT) {
@@ -770,37 +1040,37 @@ __global__ void __launch_bounds__((ns_max_threads<N, R>())) k_rhs_ns(const doubl
     }
   }
   __syncthreads();
-  for (int t = tid; t < nb * 5 * NP; t += nth) {
-    int el = t / (5 * NP), r = t % (5 * NP);
+  // the values of the RK stage (step start u0, accumulator) were requested
+  // before the divergence; the RK streams are read and written once per
+  // stage: non-temporal, so that they do not push the neighbour states out of
+  // L2
+#pragma unroll
+  for (int k = 0; k < ERK; ++k) {
+    const int t = tid + k * nth;
+    if (t >= nb * 5 * NP) break;
+    const int el = t / (5 * NP), r = t % (5 * NP);
     const int pr = (r / NP) * SM::NPP + ns_pidx<N, SM::PT>(r % NP);
     const R *E = sm + el * SM::TOTAL + SM::G + pr;
     double Rv = (double)E[0] + (double)E[5 * SM::NPP] + (double)E[10 * SM::NPP];
     long long i = (long long)e0 * 5 * NP + t;
     if (ep.mode == 0) {
-      dudt[i] = Rv;
+      __builtin_nontemporal_store(Rv, dudt + i);
     } else {
-      double accv = ep.first ? Rv : ep.acc[i] + ep.c * Rv;
+      const double u0v = PREF ? pu0[k] : __builtin_nontemporal_load(ep.u0 + i);
+      double accv = ep.first ? Rv : (PREF ? pac[k] : __builtin_nontemporal_load(ep.acc + i)) + ep.c * Rv;
       if (ep.last) {
-        ep.out[i] = ep.u0[i] + ep.dt6 * accv;
+        __builtin_nontemporal_store(u0v + ep.dt6 * accv, ep.out + i);
       } else {
-        ep.acc[i] = accv;
-        const double w = ep.u0[i] + ep.a * Rv;
+        __builtin_nontemporal_store(accv, ep.acc + i);
+        const double w = u0v + ep.a * Rv;
         if (ch.out_r) {
-          // next stage state, as the next kernel would round it; the state
-          // region of LDS is dead here and takes it for the trace records
-          const R wr = (R)(w - a.U0[r / NP]);
-          ch.out_r[i] = wr;
-          sm[el * SM::TOTAL + SM::U + pr] = wr;
+          // next stage state, as the next kernel would round it
+          ch.out_r[i] = (R)(w - (r < NP ? a.U0[0] : (r >= 4 * NP ? a.U0[4] : 0.0)));
         } else {
-          ep.out[i] = w;
+          __builtin_nontemporal_store(w, ep.out + i);
         }
       }
     }
-  }
-  if (ch.out_r) {
-    __syncthreads();
-    ns_trace_record<N, SM::PT, R>(sm, SM::TOTAL, SM::U, SM::TNN, epb, nb, op, tid, nth);
-    ns_store_records<N, R>(sm, SM::TOTAL, SM::TNN, ch.xnext, e0, nb, tid, nth);
   }
 }
 
@@ -859,6 +1129,8 @@ NsOps<N, R> make_ns_ops(const double *t) {
     for (int j = 0; j <= N; ++j) op.M[i][j] = (R)t[O.M + i * (N + 1) + j];
   op.kap[0] = (R)t[O.kap];
   op.kap[1] = (R)t[O.kap + 1];
+  op.kapx[0] = (R)t[O.kapx];
+  op.kapx[1] = (R)t[O.kapx + 1];
   for (int i = 0; i < N; ++i) {
     for (int c = 0; c < N; ++c)
       op.A[i][c] = (R)(t[O.D + i * N + c] - 0.5 * (t[O.Mc + i] * t[O.Lend + c] + t[O.Mc + N + i] * t[O.Lend + N + c]));
