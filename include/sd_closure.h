@@ -45,6 +45,22 @@ int sd_mlp_round_weights(const sd_mlp_shape *shape, const float *P, uint16_t *Wb
 int sd_mlp_forward(const sd_mlp_shape *shape, const float *P, const uint16_t *Wb, const float *X, int batch,
                    float *Y, void *work, void *stream);
 
+/* The forward pass of sd_mlp_forward without the workspace argument and
+ * without any device allocation, for callers that cannot allocate (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * The activations go to a static device array of the library (16 MiB, one
+ * per GPU, held until the process ends); the caller still owns X and Y.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (several streams or threads) race, and the activations are not kept for a
+ * backward pass.  The activations of a batch B take five buffers, each
+ * rounded up to 256 bytes: 2 B n_in, 2 B n_hidden twice (BF16 layer inputs)
+ * and 4 B n_hidden twice (FP32 pre-activations), i.e. about
+ * 2 n_in + 12 n_hidden bytes per sample (B <= 7 700 for 320-128-320).  A
+ * batch that does not fit is rejected with SD_EINVAL and nothing is
+ * launched. */
+int sd_mlp_forward_noalloc(const sd_mlp_shape *shape, const float *P, const uint16_t *Wb, const float *X, int batch,
+                           float *Y, void *stream);
+
 /* Grad [param_count] = d(sum dY . Y)/dP for the forward pass whose
  * activations are in work (weights as their BF16 values, the roundings of
  * the forward pass treated as fixed); products in FP32. */

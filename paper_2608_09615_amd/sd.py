@@ -20,6 +20,7 @@ EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state
            "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
            "sd_last_error",
            "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
+           "sd_mlp_forward_noalloc",
            "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
            "sd_bloch"]
 
@@ -105,6 +106,7 @@ def load_library(path=LIB_PATH):
     L.sd_mlp_work_bytes.restype = ctypes.c_longlong
     L.sd_mlp_round_weights.argtypes = [sp, vp, vp, vp]
     L.sd_mlp_forward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.sd_mlp_forward_noalloc.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp]
     L.sd_mlp_backward.argtypes = [sp, vp, vp, vp, ctypes.c_int, vp, vp]
     L.sd_mse.argtypes = [vp, vp, vp, ctypes.c_longlong, ctypes.c_int, vp, vp, vp]
     L.sd_mlp_adam.argtypes = [sp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
@@ -119,7 +121,7 @@ def load_library(path=LIB_PATH):
     for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
               "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
               "sd_mlp_round_weights",
-              "sd_mlp_forward",
+              "sd_mlp_forward", "sd_mlp_forward_noalloc",
               "sd_mlp_backward", "sd_mse", "sd_mlp_adam", "sd_filter", "sd_closure_set", "sd_closure_rejected",
               "sd_bloch"):
         getattr(L, f).restype = ctypes.c_int
@@ -325,6 +327,13 @@ class Mlp:
             Y = torch.empty((B, self.shape.n_out), dtype=torch.float32, device="cuda")
         _check(load_library().sd_mlp_forward(ctypes.byref(self.shape), _ptr(self.P), _ptr(self.Wb), _ptr(X), B,
                                              _ptr(Y), _ptr(self.work(B)), _stream()))
+        return Y
+
+    def forward_noalloc(self, X, Y):
+        """Forward pass into the caller's ``Y`` with the library's static
+        activation workspace (no device allocation by the library)."""
+        _check(load_library().sd_mlp_forward_noalloc(ctypes.byref(self.shape), _ptr(self.P), _ptr(self.Wb), _ptr(X),
+                                                     X.shape[0], _ptr(Y), _stream()))
         return Y
 
     def backward(self, dY):
