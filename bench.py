@@ -416,6 +416,9 @@ def main():
     rbf = run_path(torch, W, args, "bf16x3", U0, dt) if "bf16x3" in precs else None
     if rbf:
         print(f"bench: bf16x3 {rbf['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
+    rfm = run_path(torch, W, args, "fp32mfma", U0, dt) if "fp32mfma" in precs else None
+    if rfm:
+        print(f"bench: fp32mfma {rfm['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
     if r32 is None or r64 is None:
         return
     kerr, tke = ke_error(torch, W, args, U0, dt, args.ke_steps) if args.ke_steps > 0 else (None, 0.0)

@@ -57,8 +57,12 @@ extern "C" {
 typedef enum { SD_BR1 = 0, SD_COMPACT = 1 } sd_scheme;
 typedef enum { SD_DIFFUSION = 0, SD_PME = 1, SD_NAVIER_STOKES = 2 } sd_physics;
 /* Arithmetic of the contractions and fluxes.  The public state, the RHS and
- * the RK accumulation stay FP64 in every mode. */
-typedef enum { SD_FP64 = 0, SD_FP32 = 1, SD_BF16X3 = 2 } sd_precision;
+ * the RK accumulation stay FP64 in every mode.  SD_FP32: FP32 on the vector
+ * units.  SD_BF16X3: as SD_FP32, with the gradient and divergence line
+ * contractions as three BF16 products on the matrix cores (3-D
+ * Navier-Stokes only).  SD_FP32_MFMA: as SD_FP32, with those contractions on
+ * the FP32 matrix instruction (3-D Navier-Stokes only). */
+typedef enum { SD_FP64 = 0, SD_FP32 = 1, SD_BF16X3 = 2, SD_FP32_MFMA = 3 } sd_precision;
 /* Time integrator of sd_rk_step: classical RK4 (4 stages), or the
  * five-stage, fourth-order strong-stability-preserving scheme of Spiteri and
  * Ruuth that section 4.4 integrates the TGV with (Shu-Osher form, published

@@ -130,6 +130,36 @@ __device__ __forceinline__ void split_matvec(const uint16_t (*Ohi)[W], const uin
   }
 }
 
+// FP32 matrix-core variant (precision SD_FP32_MFMA): the same column
+// organisation on the 16-block 4x4x1 FP32 matrix instruction, one
+// instruction per K step and 4-row chunk.  The gradient operator is extended
+// by the neighbour-trace columns, [A | Mc0/2 | Mc1/2] acting on
+// [x; tn0; tn1], so the whole line contraction is on the matrix core; the
+// divergence uses M.  Rows padded to multiples of 4.
+template <int N>
+struct alignas(16) NsF32Ops {
+  static constexpr int RC = (N + 3) / 4;
+  static constexpr int KG = N + 2, KD = N + 1;
+  float G[4 * RC][KG];
+  float D[4 * RC][KD];
+};
+
+typedef float mf_f32x4v __attribute__((ext_vector_type(4)));
+
+// y[0 .. 4 RC) = Op x for this lane's column x[0 .. K); Op rows in LDS
+template <int K, int RC, int W>
+__device__ __forceinline__ void f32_matvec(const float (*Op)[W], const float *x, float *y, int lane) {
+  const int i = lane & 3;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) {
+    mf_f32x4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(Op[4 * r + i][k], x[k], acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[4 * r + j] = acc[j];
+  }
+}
+
 // Point values of an element in LDS: x-lines of N values at pitch PT
 // (PT = N + 1 in k_rhs_ns, so that the lines read by one wavefront spread
 // over the LDS banks; PT = N in k_traces_ns).  Point (i, j, k) sits at
@@ -817,13 +847,16 @@ __host__ __device__ constexpr int ns_waves_per_simd() {
   return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
-template <int N, typename R, bool COMPACT, bool SPLIT = false>
+// MM: 0 vector units; 1 BF16x3 split precision on the BF16 matrix cores;
+// 2 FP32 on the FP32 matrix cores (gradient and divergence contractions)
+template <int N, typename R, bool COMPACT, int MM = 0>
 __global__ void __launch_bounds__((ns_threads<N, R>()))
 __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(const double *__restrict__ U,
                                                                  double *__restrict__ dudt, KArgs a,
-                                                                 NsOps<N, R> op, RkEpi ep, NsSplitOps<N> spo,
+                                                                 NsOps<N, R> op, RkEpi ep, NsSplitOps<N> spo, NsF32Ops<N> fpo,
                                                                  NsChain<R> ch) {
-  static_assert(!SPLIT || sizeof(R) == 4, "BF16x3 works on the FP32 kernel");
+  constexpr bool SPLIT = MM == 1, MF32 = MM == 2;
+  static_assert(MM == 0 || sizeof(R) == 4, "BF16x3 and FP32 matrix-core variants work on the FP32 kernel");
   using SM = NsSmem<N>;
   constexpr int NP = SM::NP, NF = SM::NF;
   constexpr int NNB = ns_nnb<COMPACT>();
@@ -831,12 +864,18 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
   R *sm = reinterpret_cast<R *>(smem_ns);
   __shared__ int snb[ns_epb<N, R>()][NNB];
   __shared__ NsSplitOps<SPLIT ? N : 1> ssp;
+  __shared__ NsF32Ops<MF32 ? N : 1> sfp;
   constexpr int nth = ns_threads<N, R>();          // == blockDim.x
   const int tid = threadIdx.x;
   if constexpr (SPLIT) {
     constexpr int WORDS = sizeof(NsSplitOps<N>) / 4;
     for (int t = tid; t < WORDS; t += nth)
       reinterpret_cast<uint32_t *>(&ssp)[t] = reinterpret_cast<const uint32_t *>(&spo)[t];
+  }
+  if constexpr (MF32) {
+    constexpr int WORDS = sizeof(NsF32Ops<N>) / 4;
+    for (int t = tid; t < WORDS; t += nth)
+      reinterpret_cast<uint32_t *>(&sfp)[t] = reinterpret_cast<const uint32_t *>(&fpo)[t];
   }
   constexpr int epb = ns_epb<N, R>();              // == a.epb
   const long long nblocks = (a.ne + epb - 1) / epb;
@@ -903,6 +942,38 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
         for (int ai = 0; ai < N; ++ai)
           E[SM::G + (m * 5 + v) * SM::NPP + base + ai * stride] =
               th * (y[ai] + R(0.5) * (op.Mc[0][ai] * tn0 + op.Mc[1][ai] * tn1));
+      }
+    }
+  } else if constexpr (MF32) {
+    // one column per (direction, element, variable, line):
+    // g = (2/h_m) [A x + (Mc0 tn0 + Mc1 tn1) / 2] as one contraction over
+    // [x; tn0; tn1] on the FP32 matrix instruction
+    using FO = NsF32Ops<N>;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+    const int ncol = 3 * epb * 5 * NF;
+    for (int b0 = wave * 64; b0 < ncol; b0 += nwaves * 64) {
+      const int col = b0 + lane;
+      const int m = col / (epb * 5 * NF), r0 = col % (epb * 5 * NF);
+      const int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
+      const bool ok = col < ncol && el < nb;
+      float x[FO::KG];
+      int base = 0, stride = 0;
+      R *E = sm + (ok ? el : 0) * SM::TOTAL;
+#pragma unroll
+      for (int c = 0; c < FO::KG; ++c) x[c] = 0.0f;
+      if (ok) {
+        ns_line<N, SM::PT>(m, q, base, stride);
+#pragma unroll
+        for (int c = 0; c < N; ++c) x[c] = E[SM::U + v * SM::NPP + base + c * stride];
+        x[N] = E[SM::TNN + ((2 * m) * 10 + v) * NF + q];
+        x[N + 1] = E[SM::TNN + ((2 * m + 1) * 10 + v) * NF + q];
+      }
+      float y[4 * FO::RC];
+      f32_matvec<FO::KG, FO::RC>(sfp.G, x, y, lane);
+      if (ok) {
+        const R th = (R)pick(m, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
+#pragma unroll
+        for (int ai = 0; ai < N; ++ai) E[SM::G + (m * 5 + v) * SM::NPP + base + ai * stride] = th * y[ai];
       }
     }
   } else
@@ -1027,6 +1098,35 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
         for (int ai = 0; ai < N; ++ai) E[SM::G + (d * 5 + v) * SM::NPP + base + ai * stride] = -thd * y[ai];
       }
     }
+  } else if constexpr (MF32) {
+    using FO = NsF32Ops<N>;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+    const int ncol = 3 * epb * 5 * NF;
+    for (int b0 = wave * 64; b0 < ncol; b0 += nwaves * 64) {
+      const int col = b0 + lane;
+      const int d = col / (epb * 5 * NF), r0 = col % (epb * 5 * NF);
+      const int el = r0 / (5 * NF), w = r0 % (5 * NF), v = w / NF, q = w % NF;
+      const bool ok = col < ncol && el < nb;
+      float F[N + 1];
+      int base = 0, stride = 0;
+      R *E = sm + (ok ? el : 0) * SM::TOTAL;
+#pragma unroll
+      for (int c = 0; c <= N; ++c) F[c] = 0.0f;
+      if (ok) {
+        ns_line<N, SM::PT>(d, q, base, stride);
+        F[0] = E[SM::FH + ((2 * d) * 5 + v) * NF + q];
+        F[N] = E[SM::FH + ((2 * d + 1) * 5 + v) * NF + q];
+#pragma unroll
+        for (int c = 1; c < N; ++c) F[c] = E[SM::FI + ((d * (N - 1) + c - 1) * NF + q) * 5 + v];
+      }
+      float y[4 * FO::RC];
+      f32_matvec<N + 1, FO::RC>(sfp.D, F, y, lane);
+      if (ok) {
+        const R thd = (R)pick(d, a.two_over_h[0], a.two_over_h[1], a.two_over_h[2]);
+#pragma unroll
+        for (int ai = 0; ai < N; ++ai) E[SM::G + (d * 5 + v) * SM::NPP + base + ai * stride] = -thd * y[ai];
+      }
+    }
   } else
   for (int t = tid; t < 3 * epb * 5 * NF; t += nth) {
     int d = t / (epb * 5 * NF), r0 = t % (epb * 5 * NF);
@@ -1109,6 +1209,23 @@ NsSplitOps<N> make_split_ops(const double *t) {
     for (int c = 0; c <= N; ++c) put(&s.Mhi[i][c], &s.Mlo[i][c], t[O.M + i * (N + 1) + c]);
   }
   return s;
+}
+
+// Operators of the FP32 matrix-core variant: the gradient operator
+// A = D - (Mc0 Lend0^T + Mc1 Lend1^T)/2 with the neighbour-trace columns
+// Mc0/2, Mc1/2 appended, and the divergence operator M, rounded to FP32.
+template <int N>
+NsF32Ops<N> make_f32_ops(const double *t) {
+  const OpsLayout O = ops_layout(N);
+  NsF32Ops<N> f{};
+  for (int i = 0; i < N; ++i) {
+    for (int c = 0; c < N; ++c)
+      f.G[i][c] = (float)(t[O.D + i * N + c] - 0.5 * (t[O.Mc + i] * t[O.Lend + c] + t[O.Mc + N + i] * t[O.Lend + N + c]));
+    f.G[i][N] = (float)(0.5 * t[O.Mc + i]);
+    f.G[i][N + 1] = (float)(0.5 * t[O.Mc + N + i]);
+    for (int c = 0; c <= N; ++c) f.D[i][c] = (float)t[O.M + i * (N + 1) + c];
+  }
+  return f;
 }
 
 template <int N, typename R>

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsd.so")
 SD_OK, SD_EINVAL, SD_ENOMEM, SD_EHIP, SD_ENONFINITE, SD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SCHEMES = {"br1": 0, "compact": 1}
 PHYSICS = {"diffusion": 0, "pme": 1, "ns": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32mfma": 3}
 INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",

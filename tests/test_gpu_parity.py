@@ -157,6 +157,23 @@ def test_ns_entropy_fix_branch_parity(torch_cuda, oracle_lib, scheme, p):
     assert relerr(R32, Ro) < FP32_TOL_NS
 
 
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 7])
+def test_3d_ns_parity_fp32_mfma(torch_cuda, oracle_lib, scheme, p):
+    """FP32 with the gradient and divergence line contractions on the FP32
+    matrix instruction (4x4x1, one K step per instruction): same tolerance as
+    the vector FP32 path; p = 4, 5 and 7 take two row chunks."""
+    prm = oracle_lib.make_params("ns", Re=1600.0)
+    lo, hi = W.tgv_domain()
+    nel = (4, 3, 5)
+    U = W.perturbed_tgv_state(nel, p, seed=50 + p, noise=1e-3)
+    R, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp32mfma", lo, hi)
+    Ro = oracle_lib.rhs_3d(U, nel, lo, hi, p, scheme, prm)
+    err = relerr(R, Ro)
+    print(f"fp32 matrix-core NS p={p} {scheme}: normwise relative error {err:.3e}")
+    assert err < FP32_TOL_NS
+
+
 def test_ns_p7_runs_in_fp32_only(torch_cuda):
     """p = 7 needs one element's 24 480 LDS values per block: 98 KB in FP32
     and BF16x3, 191 KB in FP64, beyond the 160 KB of a compute unit."""
@@ -200,7 +217,7 @@ def test_rk4_step_parity(torch_cuda, oracle_lib, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["br1", "compact"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp32mfma"])
 def test_chained_rk_step_matches_rhs_sequence(torch_cuda, scheme, precision):
     """sd_rk_step keeps the stage state in compute precision and lets each
     stage emit the next stage's traces; that must reproduce classical RK4
