@@ -669,6 +669,9 @@ __device__ __forceinline__ void ns_prologue(const Src &src, const NsTraceOps<N, 
   // unrolled at compile time, so the reads of a line sit at constant offsets
   // from one address; work items past the end read valid data of the first
   // item and store nothing, so the reads need no branches.
+  // values per vector read of a contiguous x-run of N values (aligned: every
+  // run starts at a multiple of N within an element of 5 N^3 values)
+  constexpr int WN = sizeof(R) == 4 ? (N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1)) : (N % 2 == 0 ? 2 : 1);
   constexpr int FCNT = epb * 2 * 5 * NF, FRND = (FCNT + nth - 1) / nth;
   constexpr int NL = COMPACT ? N : 2 * N;
   struct FaceBuf {
@@ -686,12 +689,20 @@ __device__ __forceinline__ void ns_prologue(const Src &src, const NsTraceOps<N, 
       ns_line<N, N>(D, q, base, stride);
       const int elc = el < nb ? el : 0;
       const long long o = (long long)snb[elc][2 * D + S] * 5 * NP + v * NP + base;
+      auto line = [&](long long oo, R *x) __attribute__((always_inline)) {
+        if constexpr (ST == 1) {
+          // an x-line is contiguous: vector reads
 #pragma unroll
-      for (int c = 0; c < N; ++c) b.x[it][c] = src(o + c * ST, v);
+          for (int c = 0; c < N; c += WN) src.vec(oo + c, v, x + c, std::integral_constant<int, WN>{});
+        } else {
+#pragma unroll
+          for (int c = 0; c < N; ++c) x[c] = src(oo + c * ST, v);
+        }
+      };
+      line(o, b.x[it]);
       if constexpr (!COMPACT) {
         const long long o2 = (long long)snb[elc][18 + 2 * D + S] * 5 * NP + v * NP + base;
-#pragma unroll
-        for (int c = 0; c < N; ++c) b.x[it][N + c] = src(o2 + c * ST, v);
+        line(o2, b.x[it] + N);
       }
     }
   };
@@ -765,9 +776,17 @@ __device__ __forceinline__ void ns_prologue(const Src &src, const NsTraceOps<N, 
       const int elc = el < nb ? el : 0;
       const long long o = (long long)snb[elc][6 + 4 * P + e4] * 5 * NP + v * NP + at * ST;
 #pragma unroll
-      for (int c2 = 0; c2 < N; ++c2)
+      for (int c2 = 0; c2 < N; ++c2) {
+        if constexpr (SL == 1) {
+          // the lo direction is x: each run of N values is contiguous
 #pragma unroll
-        for (int c1 = 0; c1 < N; ++c1) b.x[it][c2 * N + c1] = src(o + c1 * SL + c2 * SH, v);
+          for (int c1 = 0; c1 < N; c1 += WN)
+            src.vec(o + c1 + c2 * SH, v, b.x[it] + c2 * N + c1, std::integral_constant<int, WN>{});
+        } else {
+#pragma unroll
+          for (int c1 = 0; c1 < N; ++c1) b.x[it][c2 * N + c1] = src(o + c1 * SL + c2 * SH, v);
+        }
+      }
     }
   };
   auto edges_compute = [&](auto Pc, const EdgeBuf &b) __attribute__((always_inline)) {
@@ -777,21 +796,23 @@ __device__ __forceinline__ void ns_prologue(const Src &src, const NsTraceOps<N, 
       const int t = tid + it * nth;
       const int el = t / (20 * N), r = t % (20 * N), e4 = r / (5 * N), w = r % (5 * N), v = w / N, at = w % N;
       const bool slo = (e4 >> 1) != 0, shi = (e4 & 1) != 0;
-      // both sides' sums formed, one selected
-      R a0 = R(0), a1 = R(0);
+      // the rows of the two interpolations, selected per lane (the neighbour
+      // sides are 1 - slo and 1 - shi); the rows are register values here
+      R rl[N], rh[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        rl[c] = slo ? op.Lend[0][c] : op.Lend[1][c];
+        rh[c] = shi ? op.Lend[0][c] : op.Lend[1][c];
+      }
+      R acc = R(0);
 #pragma unroll
       for (int c2 = 0; c2 < N; ++c2) {
-        R i0 = R(0), i1 = R(0);
+        R inner = R(0);
 #pragma unroll
-        for (int c1 = 0; c1 < N; ++c1) {
-          i0 += op.Lend[0][c1] * b.x[it][c2 * N + c1];
-          i1 += op.Lend[1][c1] * b.x[it][c2 * N + c1];
-        }
-        const R inner = slo ? i0 : i1;
-        a0 += op.Lend[0][c2] * inner;
-        a1 += op.Lend[1][c2] * inner;
+        for (int c1 = 0; c1 < N; ++c1) inner += rl[c1] * b.x[it][c2 * N + c1];
+        acc += rh[c2] * inner;
       }
-      if (t < ECNT && el < nb) sm[el * SM::TOTAL + SM::E + ((4 * P + e4) * 5 + v) * N + at] = shi ? a0 : a1;
+      if (t < ECNT && el < nb) sm[el * SM::TOTAL + SM::E + ((4 * P + e4) * 5 + v) * N + at] = acc;
     }
   };
   using I0 = std::integral_constant<int, 0>;
