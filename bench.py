@@ -58,7 +58,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall time of the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (calibrates byte counters)")
-    ap.add_argument("--precisions", default="fp32,fp64", help="fp32 and fp64 always for the JSON line; bf16x3 optional")
+    ap.add_argument("--precisions", default="fp32,fp64,bf16x3,fp32mfma",
+                    help="FP32 (vector), FP64, BF16x3 and FP32 matrix-core paths; fp32 and fp64 are needed for the "
+                         "JSON line")
     ap.add_argument("--bloch-theta", type=int, default=1 << 16,
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
     ap.add_argument("--curv-nel", type=int, default=32,
@@ -74,6 +76,8 @@ def parse():
 # launch configuration, with the compiler flags (any change there invalidates
 # the counter record)
 TRAFFIC_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispatch.inc", "sd_operators.cpp"]
+# dense peaks of the matrix instructions the variants use
+PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
 CURV_TRAFFIC_SOURCES = ["sd_curv_kernel.h", "sd_curv.inc", "sd_internal.h", "sd_operators.cpp"]
@@ -84,21 +88,14 @@ CLOSURE_TRAFFIC_SOURCES = ["sd_closure.inc", "sd_mlp.h", "sd_internal.h"]
 
 
 def sources_sha256(names=None):
-    import hashlib
-    from paper_2608_09615_amd.build import HIPCC_FLAGS
-    h = hashlib.sha256()
-    h.update(" ".join(HIPCC_FLAGS).encode())
-    for name in names or TRAFFIC_SOURCES:
-        h.update(name.encode())
-        with open(os.path.join(ROOT, "paper_2608_09615_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    from paper_2608_09615_amd.build import sources_sha256 as sha
+    return sha(names or TRAFFIC_SOURCES)
 
 
-def measured_traffic(args, precision):
-    """HBM bytes per RK stage (k_traces_ns + k_rhs_ns) from the committed
-    FETCH_SIZE / WRITE_SIZE counter runs, or None when the workload differs or
-    a kernel source has changed since the counters were taken."""
+def rhs_record(args):
+    """The committed counter record of k_rhs_ns on the 32^3 p = 3 compact
+    workload, or None when the workload differs or a kernel source has
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "rhs_traffic_tgv32p3.json")
     if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip
             and args.integrator == "rk4" and os.path.exists(path)):
@@ -107,7 +104,43 @@ def measured_traffic(args, precision):
         rec = json.load(f)
     if sources_sha256() != rec["sources_sha256"]:
         return None
-    return rec["per_stage_bytes"].get(precision)
+    return rec
+
+
+def measured_traffic(args, precision):
+    """HBM bytes per RK stage (one k_rhs_ns launch) from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None (see rhs_record)."""
+    rec = rhs_record(args)
+    return None if rec is None else rec["per_stage_bytes"].get(precision)
+
+
+def mfma_use(args, precision, rhs_ms):
+    """Matrix-instruction use of a variant from the committed counter record:
+    SQ_INSTS_MFMA per launch, the flops one instruction does, and the rate
+    over the live launch time against the instruction type's dense peak."""
+    rec = rhs_record(args)
+    if rec is None or precision not in rec.get("mfma_insts_per_launch", {}):
+        return None
+    n = rec["mfma_insts_per_launch"][precision]
+    flop, peak = (2048.0, PEAK_BF16_TFLOPS) if precision == "bf16x3" else (512.0, PEAK_FP32_MFMA_TFLOPS)
+    rate = n * flop / (rhs_ms * 1e-3) / 1e12
+    return {"insts_per_launch": n, "flop_per_inst": flop, "tflops": rate, "peak": peak, "mfma_frac": rate / peak,
+            "instruction": "v_mfma_f32_4x4x4_16b_bf16" if precision == "bf16x3" else "v_mfma_f32_4x4x1_16b_f32"}
+
+
+def ke_record(args):
+    """The committed t* = 20 kinetic-energy / enstrophy record of the 32^3
+    p = 3 compact workload (histories of every precision against FP64), or
+    None when the workload differs or the kernel sources have changed."""
+    path = os.path.join(ROOT, "profiles", "ke_history_tgv32p3.json")
+    if not (args.nel == 32 and args.p == 3 and args.scheme == "compact" and not args.eta_ip
+            and args.integrator == "rk4" and args.Re == 1600.0 and os.path.exists(path)):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if sources_sha256(rec["sources"]) != rec["sources_sha256"]:
+        return None
+    return {"t_end": rec["t_end"], "command": rec["command"], "errors_vs_fp64": rec["errors"]}
 
 
 def run_path(torch, W, args, precision, U0, dt):
@@ -166,7 +199,12 @@ def ke_error(torch, W, args, U0, dt, nsteps):
     return max(abs(a - b) for a, b in zip(k32, k64)) / k64[0], nsteps * dt
 
 
-def cpu_baseline(W, args, U0):
+def cpu_baseline(W, args, U0, R_gpu64=None):
+    """The FP64 oracle on the host cores: the same RHS on a sample of the
+    workload's elements, with every host thread (at most 16) and with one
+    thread.  With R_gpu64 (the GPU FP64 RHS of U0) the leg also states, per
+    variable, the largest difference on the sampled elements relative to the
+    oracle's largest value, and that figure over 1e-12."""
     import numpy as np
     from oracle import oracle as O
     lo, hi = W.tgv_domain()
@@ -176,19 +214,48 @@ def cpu_baseline(W, args, U0):
     n = min(args.cpu_sample, ne)
     sel = np.arange(n, dtype=np.int64)
     prm = O.make_params("ns", Re=args.Re, Ma=0.1, Pr=0.71)
-    # repeated right-hand sides until about cpu_seconds of work (at least one)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.rhs_3d_elems(U0, nel, lo, hi, args.p, args.scheme, prm, sel, nthreads=threads)
-        reps += 1
-        sec = time.perf_counter() - t0
-        if sec >= args.cpu_seconds or reps >= 100:
-            break
-    return {"value": reps * n * (args.p + 1) ** 3 / sec / 1e9, "unit": "GDOF/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{reps} RHS evaluations on the first {n} of {ne} elements of the same TGV state "
-                      f"({sec:.1f} s wall, OpenMP over elements)"}
+
+    # every FP64 evaluation carries the rounding of its input: the input moved
+    # by about one ulp (seeded) gives the oracle's own sensitivity, evaluated
+    # in alternate repetitions of the timed loop (same cost)
+    U0p = U0 * (1.0 + 2.2e-16 * np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, U0.shape))
+
+    def timed(nthreads, elems, seconds):
+        # repeated right-hand sides until about `seconds` of work (at least two)
+        reps, out = 0, [None, None]
+        t0 = time.perf_counter()
+        while True:
+            out[reps % 2] = O.rhs_3d_elems(U0 if reps % 2 == 0 else U0p, nel, lo, hi, args.p, args.scheme, prm,
+                                           elems, nthreads=nthreads)
+            reps += 1
+            sec = time.perf_counter() - t0
+            if reps >= 2 and (sec >= seconds or reps >= 100):
+                return reps, sec, out
+
+    reps, sec, (Ro, Rop) = timed(threads, sel, args.cpu_seconds)
+    n1 = min(n, 4096)
+    reps1, sec1, _ = timed(1, sel[:n1], max(2.0, args.cpu_seconds / 4))
+    dof_el = (args.p + 1) ** 3
+    out = {"value": reps * n * dof_el / sec / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+           "sample": f"{reps} RHS evaluations on the first {n} of {ne} elements of the same TGV state "
+                     f"({sec:.1f} s wall, OpenMP over elements)",
+           "single_thread": {"value": reps1 * n1 * dof_el / sec1 / 1e9, "unit": "GDOF/s", "cores": 1,
+                             "sample": f"{reps1} RHS evaluations on the first {n1} elements ({sec1:.1f} s wall)"}}
+    if R_gpu64 is not None:
+        Ro = np.asarray(Ro).reshape(n, 5, -1)
+        Rop = np.asarray(Rop).reshape(n, 5, -1)
+        Rg = np.asarray(R_gpu64).reshape(ne, 5, -1)[:n]
+        scale = [float(np.abs(Ro[:, v]).max()) for v in range(5)]
+        err = [float(np.abs(Rg[:, v] - Ro[:, v]).max()) / scale[v] for v in range(5)]
+        sens = [float(np.abs(Rop[:, v] - Ro[:, v]).max()) / scale[v] for v in range(5)]
+        out["fp64_parity"] = {
+            "per_variable": err, "over_1e-12": [e / 1e-12 for e in err],
+            "oracle_one_ulp_sensitivity": sens,
+            "bar": [max(1e-12, 4.0 * x) for x in sens],
+            "within_bar": all(e < max(1e-12, 4.0 * x) for e, x in zip(err, sens)),
+            "sample": f"first {n} elements, the workload's initial state (max|R| per variable: "
+                      + ", ".join(f"{x:.2e}" for x in scale) + ")"}
+    return out
 
 
 BLOCH_TIMES = (0.01, 0.1, 1.0)
@@ -373,6 +440,18 @@ def curv_traffic(N, p, scheme):
     return rec["bytes_per_rhs"]
 
 
+def fp64_rhs(torch, args, U0):
+    """One FP64 right-hand side of the workload's initial state (host copy)."""
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd import workloads as W
+    lo, hi = W.tgv_domain()
+    sd = SD((args.nel,) * 3, args.p, scheme=args.scheme, physics="ns", precision="fp64", lo=lo, hi=hi,
+            Re=args.Re, Ma=0.1, Pr=0.71, gamma=1.4, eta_ip=args.eta_ip)
+    R = sd.rhs(torch.from_numpy(U0).to("cuda")).cpu().numpy()
+    sd.close()
+    return R
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -421,6 +500,8 @@ def main():
         print(f"bench: fp32mfma {rfm['gdofs']:.2f} GDOF/s", file=sys.stderr, flush=True)
     if r32 is None or r64 is None:
         return
+    # the headline FP32 figure is the faster of the two FP32 variants
+    best32, path32 = (rfm, "matrix cores (fp32mfma)") if rfm and rfm["gdofs"] > r32["gdofs"] else (r32, "vector")
     kerr, tke = ke_error(torch, W, args, U0, dt, args.ke_steps) if args.ke_steps > 0 else (None, 0.0)
     dof = args.nel ** 3 * (args.p + 1) ** 3
     flop = FLOP_PER_DOF.get(args.p, 1430.0) * dof
@@ -443,12 +524,12 @@ def main():
 
     rec = {
         "metric": "SD RHS GDOF/s per RK stage",
-        "value": r32["gdofs"],
+        "value": best32["gdofs"],
         "unit": "GDOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["ms_per_step"],
+        "ms_per_step": best32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -459,14 +540,23 @@ def main():
                    "dof": dof,
                    "step": ("one SSP-RK(5,4) step = 5 RHS + 5 FP64 stage combinations" if args.integrator == "ssprk54"
                             else "one RK4 step = 4 RHS + 4 FP64 stage updates"),
-                   "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke},
-        "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "fp32"),
+                   "fp32_path": path32,
+                   "ke_error_fp32_vs_fp64": kerr, "ke_error_t_end": tke,
+                   "ke_error_t20": ke_record(args)},
+        "roofline": roof(best32, PEAK_FP32_TFLOPS, "k_rhs_ns", "fp32mfma" if best32 is rfm else "fp32"),
+        "fp32_vector": {"value": r32["gdofs"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+                        "roofline": roof(r32, PEAK_FP32_TFLOPS, "k_rhs_ns", "fp32")},
         "fp64": {"value": r64["gdofs"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
-                 "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_traces+k_rhs", "fp64")},
+                 "roofline": roof(r64, PEAK_FP64_TFLOPS, "k_rhs_ns", "fp64")},
     }
+    if rfm:
+        rec["fp32_mfma"] = {"value": rfm["gdofs"], "ms_per_step": rfm["ms_per_step"], "dtype": "f32",
+                            "roofline": roof(rfm, PEAK_FP32_TFLOPS, "k_rhs_ns", "fp32mfma"),
+                            "mfma": mfma_use(args, "fp32mfma", rfm["rhs_ms_avg"])}
     if rbf:
         rec["bf16x3"] = {"value": rbf["gdofs"], "ms_per_step": rbf["ms_per_step"], "dtype": "f32+bf16x3",
-                         "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_traces+k_rhs", "bf16x3")}
+                         "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_rhs_ns", "bf16x3"),
+                         "mfma": mfma_use(args, "bf16x3", rbf["rhs_ms_avg"])}
     if args.bloch_theta > 0:
         rec["bloch"] = bloch_bench(torch, args)
     if args.curv_nel > 0:
@@ -474,7 +564,7 @@ def main():
     if args.closure_nel > 0:
         rec["closure"] = closure_bench(torch, args)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(W, args, U0)
+        rec["cpu_baseline"] = cpu_baseline(W, args, U0, fp64_rhs(torch, args, U0))
     print(json.dumps(rec), flush=True)
 
 

@@ -19,6 +19,25 @@ HIPCC_FLAGS = [
 ]
 
 
+def sources_sha256(names):
+    """SHA-256 of the compiler flags and the named sources under csrc/: the key
+    of a committed measurement record (a record taken on other sources is not
+    reported)."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    for name in names:
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+# the sources that define and launch the Navier-Stokes right-hand side, its
+# operators and its launch configuration
+NS_RHS_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispatch.inc", "sd_operators.cpp"]
+
+
 def build_library(verbose=False):
     """Compile every HIP source into ``libsd.so`` (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

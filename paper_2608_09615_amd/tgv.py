@@ -2,7 +2,8 @@
 histories of one discretisation, and the error of one precision against
 another (the FP64 path is the reference of the FP32 and BF16x3 ones).
 
-    python -m paper_2608_09615_amd.tgv --nel 32 --p 3 --t-end 20 --precisions fp64,fp32
+    python -m paper_2608_09615_amd.tgv --nel 32 --p 3 --t-end 20 --precisions fp64,fp32,bf16x3,fp32mfma \
+        --record profiles/ke_history_tgv32p3.json
 
 The state is the compressible TGV (Ma = 0.1, gamma = 1.4, Pr = 0.71) on the
 periodic box [0, 2 pi]^3; every run takes RK steps of equal size, dt_out / k
@@ -75,20 +76,6 @@ def history(nel, p, scheme="compact", precision="fp64", Re=1600.0, t_end=20.0, d
             "t": t, "ke": ke, "enstrophy": ens, "wall_s": wall}
 
 
-def stability(nel, p, scheme, precision="fp32", Re=1600.0, t_end=20.0, dt_out=0.5, log=print, cfl=None):
-    """Run the TGV to t_end and report whether it stays finite (the paper's
-    stability tables): {"stable": bool, "t_fail": first output time at which
-    the state was non-finite or None, "wall_s": ...}."""
-    try:
-        r = history(nel, p, scheme, precision, Re, t_end, dt_out, log, cfl=cfl)
-        return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": True,
-                "t_fail": None, "wall_s": r["wall_s"], "ke_end": r["ke"][-1]}
-    except NonFiniteState as err:
-        t_fail = err.t
-        return {"nel": nel, "p": p, "scheme": scheme, "precision": precision, "Re": Re, "stable": False,
-                "t_fail": t_fail, "wall_s": None, "ke_end": None}
-
-
 def compare(run, ref):
     """max_t |KE - KE_ref| / KE_ref(0) and max_t |ens - ens_ref| / max_t ens_ref."""
     ke = max(abs(a - b) for a, b in zip(run["ke"], ref["ke"])) / ref["ke"][0]
@@ -108,21 +95,12 @@ def main(argv=None):
     ap.add_argument("--precisions", default="fp64,fp32", help="the first one is the reference")
     ap.add_argument("--integrator", default="rk4", choices=["rk4", "ssprk54"])
     ap.add_argument("--cfl", type=float, default=None, help="adaptive step with this Courant number")
-    ap.add_argument("--stability", action="store_true",
-                    help="run BR1 and compact in the first precision only and report whether each stays finite")
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--out", default=None, help="JSON file with every run's full histories")
+    ap.add_argument("--record", default=None,
+                    help="JSON record keyed to the kernel sources: the errors against the first precision, "
+                         "the histories every 0.5 and the wall times")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
-    if a.stability:
-        pr = a.precisions.split(",")[0]
-        res = [stability(a.nel, a.p, sch, pr, a.Re, a.t_end, a.dt_out, log, a.cfl) for sch in ("br1", "compact")]
-        for r in res:
-            log(f"tgv stability: Re={a.Re:g} {a.nel}^3 p={a.p} ({a.nel * (a.p + 1)}^3 DoF) {r['scheme']} {pr}: "
-                + ("stable" if r["stable"] else f"unstable (non-finite by t={r['t_fail']:.2f})"))
-        if a.out:
-            with open(a.out, "w") as f:
-                json.dump(res, f)
-        return
     runs = [history(a.nel, a.p, a.scheme, pr, a.Re, a.t_end, a.dt_out, log, a.integrator, a.cfl)
             for pr in a.precisions.split(",")]
     res = {"runs": runs, "errors": {r["precision"]: compare(r, runs[0]) for r in runs[1:]}}
@@ -131,6 +109,22 @@ def main(argv=None):
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f)
+    if a.record:
+        from .build import NS_RHS_SOURCES, sources_sha256
+        every = max(1, int(round(0.5 / a.dt_out)))
+        cmd = ("python -m paper_2608_09615_amd.tgv " + " ".join(argv if argv is not None else __import__("sys").argv[1:]))
+        rec = {"workload": f"TGV Re={a.Re:g} Ma=0.1 {a.nel}^3 hex p={a.p} {a.scheme}, {a.integrator}",
+               "t_end": a.t_end, "dt_out": a.dt_out, "command": cmd,
+               "reference": runs[0]["precision"],
+               "errors": res["errors"],
+               "error_definition": "ke_err = max_t |KE - KE_ref| / KE_ref(0); enstrophy_err = max_t |ens - ens_ref| "
+                                   "/ max_t ens_ref; t every dt_out up to t_end",
+               "sources": NS_RHS_SOURCES, "sources_sha256": sources_sha256(NS_RHS_SOURCES),
+               "runs": {r["precision"]: {"dt": r["dt"], "steps": r["steps"], "wall_s": r["wall_s"],
+                                         "t": r["t"][::every], "ke": r["ke"][::every],
+                                         "enstrophy": r["enstrophy"][::every]} for r in runs}}
+        with open(a.record, "w") as f:
+            json.dump(rec, f, indent=1)
 
 
 if __name__ == "__main__":
