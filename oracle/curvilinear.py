@@ -201,3 +201,218 @@ def rhs(u, nel, Xg, p, scheme="compact", nu=1.0, eta_ip=0.0):
         G = -nu * sum(S[d][..., d, m] * vF[:, m] for m in range(3))
         R -= Jinv * _along(G, d, M)
     return R
+
+
+# ---------------------------------------------------------------------------
+# Navier-Stokes on curvilinear hexahedra (section 2.3, eqs. ns:mapped and
+# adj:f, with the fluxes of section 4.4).  State U[e][v][k][j][i], v = rho,
+# rho u, rho v, rho w, rho E.  The steps are those of `rhs` applied to the
+# five conservative variables: traces, common solution, the auxiliary
+# variable (the gradient of every conservative variable, all metric terms),
+# its one-sided (compact) or standard (BR1) interface values and their
+# average, then G_d = S_d . (F_c - F_v) at the flux points of family d and
+# the divergence.  At the interfaces the convective part is the Roe flux
+# (with Harten's fix on the acoustic waves, reading R7) along the unit normal
+# n = S_d / |S_d|, scaled by |S_d|, and the viscous part is F_v of the common
+# solution and common gradient (option (a) of section 2.1).  The pointwise
+# laws below take a direction vector instead of an axis; for an axis they are
+# the C oracle's (pinned in the tests).
+# ---------------------------------------------------------------------------
+
+def _p0(prm):
+    return prm.rho0 / prm.gamma * (prm.u0 / prm.Ma) ** 2
+
+
+def _mu(prm, T):
+    mu0 = prm.rho0 * prm.u0 * prm.Lref / prm.Re
+    if prm.sutherland_s < 0.0:
+        return mu0 * np.ones_like(T)
+    th = T / (_p0(prm) / prm.rho0)
+    return mu0 * th * np.sqrt(th) * (1.0 + prm.sutherland_s) / (th + prm.sutherland_s)
+
+
+def ns_conv_dir(prm, U, s):
+    """F_c . s for states U [..., 5] and direction vectors s [..., 3]:
+    (rho u_s, rho u u_s + P s, (rho E + P) u_s), u_s = u . s."""
+    g = prm.gamma
+    rho = U[..., 0]
+    u = U[..., 1:4] / rho[..., None]
+    P = (g - 1.0) * (U[..., 4] - 0.5 * rho * np.sum(u * u, axis=-1))
+    us = np.sum(u * s, axis=-1)
+    F = np.empty(U.shape)
+    F[..., 0] = rho * us
+    F[..., 1:4] = U[..., 1:4] * us[..., None] + P[..., None] * s
+    F[..., 4] = (U[..., 4] + P) * us
+    return F
+
+
+def ns_visc_dir(prm, U, G, s):
+    """F_v . s for states U [..., 5], gradients of the conservative variables
+    G [..., 5 (v), 3 (m)] and direction vectors s [..., 3]:
+    (0, tau s, u . tau s + kappa grad T . s), tau = mu (grad u + grad u^T)
+    + lambda (div u) I, T = P / rho (R = 1), kappa = mu C_p / Pr."""
+    g = prm.gamma
+    rho = U[..., 0]
+    u = U[..., 1:4] / rho[..., None]
+    E = U[..., 4] / rho
+    T = (g - 1.0) * (E - 0.5 * np.sum(u * u, axis=-1))
+    drho = G[..., 0, :]                                      # [..., m]
+    du = (G[..., 1:4, :] - u[..., :, None] * drho[..., None, :]) / rho[..., None, None]   # [..., i, m]
+    dE = (G[..., 4, :] - E[..., None] * drho) / rho[..., None]
+    dT = (g - 1.0) * (dE - np.einsum("...j,...jm->...m", u, du))
+    mu = _mu(prm, T)
+    lam = prm.lambda_over_mu * mu
+    kappa = mu * (g / (g - 1.0)) / prm.Pr
+    div = du[..., 0, 0] + du[..., 1, 1] + du[..., 2, 2]
+    tau = mu[..., None, None] * (du + np.swapaxes(du, -1, -2)) + (lam * div)[..., None, None] * np.eye(3)
+    ts = np.einsum("...ij,...j->...i", tau, s)
+    F = np.zeros(U.shape)
+    F[..., 1:4] = ts
+    F[..., 4] = np.sum(u * ts, axis=-1) + kappa * np.sum(dT * s, axis=-1)
+    return F
+
+
+def ns_roe_normal(prm, UL, UR, n):
+    """Roe flux along unit normals n [..., 3]: (F(UL) + F(UR)) . n / 2 -
+    sum_k |l_k| a_k r_k / 2 over the acoustic waves u_n -+ c, the entropy wave
+    and the shear waves at the square-root-density average, Harten's fix
+    |l| -> (l^2 + delta^2) / (2 delta) for |l| < delta on the acoustic pair,
+    delta = entropy_fix (|u_n| + c)."""
+    g = prm.gamma
+
+    def prim(U):
+        rho = U[..., 0]
+        u = U[..., 1:4] / rho[..., None]
+        P = (g - 1.0) * (U[..., 4] - 0.5 * rho * np.sum(u * u, axis=-1))
+        return rho, u, P, (U[..., 4] + P) / rho
+
+    rL, uL, pL, HL = prim(UL)
+    rR, uR, pR, HR = prim(UR)
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    w = 1.0 / (sL + sR)
+    ut = (sL[..., None] * uL + sR[..., None] * uR) * w[..., None]
+    Ht = (sL * HL + sR * HR) * w
+    rt = sL * sR
+    q2 = np.sum(ut * ut, axis=-1)
+    c2 = (g - 1.0) * (Ht - 0.5 * q2)
+    c = np.sqrt(c2)
+    un = np.sum(ut * n, axis=-1)
+    du = uR - uL
+    dun = np.sum(du * n, axis=-1)
+    dut = du - dun[..., None] * n
+    drho, dp = rR - rL, pR - pL
+    a1 = (dp - rt * c * dun) / (2.0 * c2)
+    a5 = (dp + rt * c * dun) / (2.0 * c2)
+    a2 = drho - dp / c2
+    l1, l2, l5 = np.abs(un - c), np.abs(un), np.abs(un + c)
+    delta = prm.entropy_fix * (np.abs(un) + c)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        fix = lambda l: np.where((delta > 0.0) & (l < delta), (l * l + delta * delta) / (2.0 * delta), l)
+        l1, l5 = fix(l1), fix(l5)
+    D = np.empty(UL.shape)
+    D[..., 0] = l1 * a1 + l2 * a2 + l5 * a5
+    D[..., 1:4] = ((l1 * a1)[..., None] * (ut - c[..., None] * n) + (l2 * a2)[..., None] * ut
+                   + (l5 * a5)[..., None] * (ut + c[..., None] * n) + (l2 * rt)[..., None] * dut)
+    D[..., 4] = (l1 * a1 * (Ht - c * un) + l2 * a2 * 0.5 * q2 + l5 * a5 * (Ht + c * un)
+                 + l2 * rt * np.sum(ut * dut, axis=-1))
+    return 0.5 * (ns_conv_dir(prm, UL, n) + ns_conv_dir(prm, UR, n)) - 0.5 * D
+
+
+def _vars_last(A):
+    """[E, 5, ...] -> [E, ..., 5]."""
+    return np.moveaxis(A, 1, -1)
+
+
+def rhs_ns(U, nel, Xg, p, scheme, prm):
+    """dU/dt for U[e][v][k][j][i] (FP64) on the mesh of node coordinates Xg:
+    the compressible Navier-Stokes equations of section 4.4 on curvilinear
+    elements (section 2.3; prm = oracle.make_params("ns", ...))."""
+    U = np.asarray(U, dtype=np.float64)
+    _, _, _, L, M = operators(p)
+    S, detJ = metrics(Xg, p)
+    Jinv = 1.0 / detJ
+    nbr = {(d, s): _neighbour(nel, d, s) for d in range(3) for s in (0, 1)}
+    nv = 5
+    comp = [U[:, v] for v in range(nv)]
+    # 1.-2. per variable: traces, common solution, continuous and one-sided
+    # solutions (as for the scalar equation)
+    uF, T, uhat, uC, uSide = [], [], [], [], []
+    for v in range(nv):
+        f = [_along(comp[v], d, L) for d in range(3)]
+        t = {(d, s): _end(f[d], d, s) for d in range(3) for s in (0, 1)}
+        h = {}
+        for d in range(3):
+            for s in (0, 1):
+                other = t[(d, 1 - s)][nbr[(d, s)]]
+                h[(d, s)] = 0.5 * (other + t[(d, s)]) if s == 0 else 0.5 * (t[(d, s)] + other)
+        C, sides = [], []
+        for d in range(3):
+            Cd = f[d].copy()
+            _set_end(Cd, d, 0, h[(d, 0)])
+            _set_end(Cd, d, 1, h[(d, 1)])
+            C.append(Cd)
+            sd_ = []
+            for s in (0, 1):
+                X = Cd.copy()
+                _set_end(X, d, 1 - s, t[(d, 1 - s)])
+                sd_.append(X)
+            sides.append(sd_)
+        uF.append(f)
+        T.append(t)
+        uhat.append(h)
+        uC.append(C)
+        uSide.append(sides)
+
+    def grad(fam):
+        # auxiliary variable of one conservative variable: [E, 3 (m), k, j, i]
+        return np.stack([Jinv * sum(_along(fam[dd] * S[dd][..., dd, m], dd, M) for dd in range(3))
+                         for m in range(3)], axis=1)
+
+    # 3. gradients at the solution points [E, 5, 3, k, j, i]
+    vS = np.stack([grad(uC[v]) for v in range(nv)], axis=1)
+    # 4. interface values of the gradient: one-sided (compact) or standard
+    vface = {}
+    for d in range(3):
+        for s in (0, 1):
+            per_v = []
+            for v in range(nv):
+                if scheme == "compact":
+                    fam = list(uC[v])
+                    fam[d] = uSide[v][d][s]
+                    g_ = grad(fam)
+                else:
+                    g_ = vS[:, v]
+                per_v.append(np.stack([_end(_along(g_[:, m], d, L), d, s) for m in range(3)], axis=1))
+            vface[(d, s)] = np.stack(per_v, axis=1)          # [E, 5, 3, a, b]
+    R = np.zeros_like(U)
+    for d in range(3):
+        Sd = S[d][..., d, :]                                 # [E, family d points..., 3]
+        # interior flux points: U and the gradient interpolated along d
+        UFd = np.stack([uF[v][d] for v in range(nv)], axis=1)                       # [E, 5, ...]
+        VFd = np.stack([np.stack([_along(vS[:, v, m], d, L) for m in range(3)], axis=1)
+                        for v in range(nv)], axis=1)                               # [E, 5, 3, ...]
+        Uv = _vars_last(UFd)                                                       # [E, ..., 5]
+        Gv = np.moveaxis(np.moveaxis(VFd, 1, -1), 1, -1)                           # [E, ..., 5, 3]
+        Gd = ns_conv_dir(prm, Uv, Sd) - ns_visc_dir(prm, Uv, Gv, Sd)               # [E, ..., 5]
+        # interfaces: Roe along the unit normal and the viscous flux of the
+        # common solution and common gradient
+        for s in (0, 1):
+            nb = nbr[(d, s)]
+            town = np.stack([T[v][(d, s)] for v in range(nv)], axis=-1)            # [E, a, b, 5]
+            toth = np.stack([T[v][(d, 1 - s)][nb] for v in range(nv)], axis=-1)
+            UL, UR = (toth, town) if s == 0 else (town, toth)
+            Uh = np.stack([uhat[v][(d, s)] for v in range(nv)], axis=-1)
+            own = vface[(d, s)]
+            oth = vface[(d, 1 - s)][nb]
+            vh = 0.5 * (oth + own) if s == 0 else 0.5 * (own + oth)                 # [E, 5, 3, a, b]
+            vh = np.moveaxis(np.moveaxis(vh, 1, -1), 1, -1)                        # [E, a, b, 5, 3]
+            Sf = _end(Sd[..., 0], d, s)
+            Sf = np.stack([_end(Sd[..., m], d, s) for m in range(3)], axis=-1)     # [E, a, b, 3]
+            nrm = np.sqrt(np.sum(Sf * Sf, axis=-1))
+            Gf = nrm[..., None] * ns_roe_normal(prm, UL, UR, Sf / nrm[..., None]) - ns_visc_dir(prm, Uh, vh, Sf)
+            for v in range(nv):
+                sub = Gd[..., v]
+                _set_end(sub, d, s, Gf[..., v])
+        for v in range(nv):
+            R[:, v] -= Jinv * _along(Gd[..., v], d, M)
+    return R

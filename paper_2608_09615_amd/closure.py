@@ -144,20 +144,53 @@ class Problem:
         return U
 
 
-def generate(torch, prob, seeds, t_end, dt_snap, log=print):
-    """Training pairs from fine runs (snapshots at t > 0): host FP64 arrays
-    X, T [samples, 5 n^3] and the snapshot number of every sample."""
+def interval_targets(torch, prob, Uc, dt_snap):
+    """Trajectory defects of the coarse scheme over the snapshot intervals:
+    for consecutive filtered fine states Uc[k], Uc[k+1] (host FP64
+    [n_el_c, 5 n^3]) the target of Uc[k] is (Uc[k+1] - Phi(Uc[k])) / dt_snap,
+    Phi the plain coarse scheme over one interval (RK4 steps of the coarse
+    step size).  A closure that adds it to the coarse right-hand side keeps
+    the coarse run on the filtered fine trajectory to first order in the
+    interval, and the averaging over the interval removes the part of the
+    instantaneous defect that the coarse state cannot predict."""
+    ncc = max(1, round(dt_snap / prob.dt_c))
+    dtc = dt_snap / ncc
+    X, T = [], []
+    for k in range(len(Uc) - 1):
+        U = torch.from_numpy(Uc[k].reshape((prob.coarse.ne, 5) + (prob.n,) * 3)).to("cuda")
+        for _ in range(ncc):
+            prob.coarse.rk_step(U, dtc)
+        X.append(Uc[k])
+        T.append((Uc[k + 1] - U.cpu().numpy().reshape(Uc[k].shape)) / dt_snap)
+    return X, T
+
+
+def generate(torch, prob, seeds, t_end, dt_snap, log=print, target="rhs"):
+    """Training pairs from fine runs: host FP64 arrays X, T [samples, 5 n^3]
+    and the snapshot number of every sample.  target "rhs": the residual
+    defect P_c R_f(U_f) - R_c(P_c U_f) at every snapshot t > 0; "interval":
+    the coarse scheme's trajectory defect over each snapshot interval
+    (interval_targets), from t = 0."""
     X, T, S = [], [], []
     for seed in seeds:
         t0 = time.perf_counter()
+        Uc = []
 
         def each(t, U):
-            if t > 0:
+            if target == "interval":
+                Uc.append(prob.filt(U).cpu().numpy().reshape(-1, prob.nve))
+            elif t > 0:
                 x, y = prob.pair(U)
                 S.append(np.full(x.shape[0], len(X)))
                 X.append(x)
                 T.append(y)
         prob.fine_run(torch, seed, t_end, dt_snap, each, log=log)
+        if target == "interval":
+            xs, ts = interval_targets(torch, prob, Uc, dt_snap)
+            for x, y in zip(xs, ts):
+                S.append(np.full(x.shape[0], len(X)))
+                X.append(x)
+                T.append(y)
         log(f"closure: fine run seed {seed} to t={t_end:.2f} in {time.perf_counter() - t0:.1f} s")
     return np.concatenate(X), np.concatenate(T), np.concatenate(S)
 
@@ -256,7 +289,7 @@ def a_priori(torch, net, Xn, Tn, batch=4096):
 VARIANTS = [("closure", 1.0, 1e-3)]
 
 
-def evaluate(torch, prob, seed, t_end, dt_snap, net, norm, variants=VARIANTS, log=print):
+def evaluate(torch, prob, seed, t_end, dt_snap, net, norm, variants=VARIANTS, log=print, target="rhs"):
     """Held-out seed: one fine run gives the filtered reference history and
     the a-priori pairs; then the coarse runs, plain and with the closure for
     each (name, max_ratio, ke_tol) of ``variants``: max_ratio bounds each
@@ -267,13 +300,23 @@ def evaluate(torch, prob, seed, t_end, dt_snap, net, norm, variants=VARIANTS, lo
     ref, apri = [], []
     t0 = time.perf_counter()
 
+    Ucs = []
+
     def each(t, U):
-        ref.append(prob.coarse.diagnostics(prob.filt(U)))
-        if t > 0:
+        Uc = prob.filt(U)
+        ref.append(prob.coarse.diagnostics(Uc))
+        if target == "interval":
+            Ucs.append(Uc.cpu().numpy().reshape(-1, prob.nve))
+        elif t > 0:
             x, y = prob.pair(U)
             xn, tn = normalise(x, y, shift, scale, out_scale, prob.nve)
             apri.append((t,) + a_priori(torch, net, xn, tn))
     Uf = prob.fine_run(torch, seed, t_end, dt_snap, each, log=log)
+    if target == "interval":
+        for k, (x, y) in enumerate(zip(*interval_targets(torch, prob, Ucs, dt_snap))):
+            xn, tn = normalise(x, y, shift, scale, out_scale, prob.nve)
+            apri.append((k * dt_snap,) + a_priori(torch, net, xn, tn))
+        del Ucs
     torch.cuda.synchronize()
     wall_fine_total = time.perf_counter() - t0
     del Uf
@@ -352,10 +395,10 @@ def evaluate(torch, prob, seed, t_end, dt_snap, net, norm, variants=VARIANTS, lo
 
 
 def train(torch, prob, seeds, t_end, dt_snap, n_sym=8, hidden=128, iters=10000, batch=1024, lr=1e-3,
-          weight_power=0.5, log=print):
+          weight_power=0.5, log=print, target="rhs"):
     """Pairs from the fine runs of ``seeds``, symmetry images, normalisation,
     snapshot weights and the fit; returns (net, normalisation, losses, samples)."""
-    X, T, snap = generate(torch, prob, seeds, t_end, dt_snap, log=log)
+    X, T, snap = generate(torch, prob, seeds, t_end, dt_snap, log=log, target=target)
     X, T, snap = augment(X, T, prob.n, n_sym, seed=12345, extra=snap)
     shift, scale, out_scale = normalisation(X, T, prob.nve)
     w = snapshot_weights(T, snap, out_scale, weight_power) if weight_power else None
@@ -368,13 +411,13 @@ def train(torch, prob, seeds, t_end, dt_snap, n_sym=8, hidden=128, iters=10000, 
 
 def run(nel_f=64, ratio=4, p=3, Re=5000.0, train_seeds=range(7), test_seed=7, t_end=4.0, dt_snap=0.5,
         n_sym=8, hidden=128, iters=10000, batch=1024, lr=1e-3, weight_power=0.5, log=print, out_path=None,
-        load=None, variants=VARIANTS):
+        load=None, variants=VARIANTS, target="rhs"):
     """Train (or load ``load`` = (params .npy, norm .json)) and evaluate."""
     import torch
     prob = Problem(nel_f, ratio, p, Re)
     cfg = {"nel_fine": nel_f, "nel_coarse": nel_f // ratio, "p": p, "Re": Re, "train_seeds": list(train_seeds),
            "test_seed": test_seed, "t_end": t_end, "dt_snap": dt_snap, "n_sym": n_sym, "hidden": hidden,
-           "iters": iters, "batch": batch, "lr": lr, "weight_power": weight_power}
+           "iters": iters, "batch": batch, "lr": lr, "weight_power": weight_power, "target": target}
     res = {"config": cfg}
     if load:
         nve = prob.nve
@@ -386,14 +429,14 @@ def run(nel_f=64, ratio=4, p=3, Re=5000.0, train_seeds=range(7), test_seed=7, t_
         res["train"] = saved.get("train")
     else:
         net, norm, losses, ns = train(torch, prob, list(train_seeds), t_end, dt_snap, n_sym, hidden, iters, batch,
-                                      lr, weight_power, log=log)
+                                      lr, weight_power, log=log, target=target)
         res["train"] = {"losses": losses, "samples": ns}
         if out_path:
             np.save(out_path.replace(".json", "_params.npy"), net.P.cpu().numpy())
             with open(out_path.replace(".json", "_norm.json"), "w") as f:
                 json.dump({"norm": norm, "train": res["train"], "config": cfg}, f)
     if test_seed is not None:
-        post = evaluate(torch, prob, test_seed, t_end, dt_snap, net, norm, variants, log=log)
+        post = evaluate(torch, prob, test_seed, t_end, dt_snap, net, norm, variants, log=log, target=target)
         res["a_priori"] = post.pop("a_priori")
         res["a_posteriori"] = post
         if variants:
@@ -426,6 +469,8 @@ def main(argv=None):
     ap.add_argument("--variants", default=None,
                     help="corrected runs as name:max_ratio:ke_tol,... (default: %s)" %
                     ",".join(f"{n}:{m}:{k}" for n, m, k in VARIANTS))
+    ap.add_argument("--target", default="rhs", choices=["rhs", "interval"],
+                    help="rhs: residual defect at each snapshot; interval: trajectory defect over each interval")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     variants = VARIANTS if a.variants is None else [
@@ -433,7 +478,7 @@ def main(argv=None):
     test_seed = None if a.no_eval else (a.train_seeds if a.test_seed is None else a.test_seed)
     res = run(a.nel_fine, a.ratio, a.p, a.Re, range(a.train_seeds), test_seed, a.t_end, a.dt_snap, a.n_sym,
               a.hidden, a.iters, a.batch, a.lr, a.weight_power, log=lambda s: print(s, flush=True), out_path=a.out,
-              load=a.load, variants=variants)
+              load=a.load, variants=variants, target=a.target)
     short = {k: res[k] for k in ("config", "a_priori", "speedup_vs_fine") if k in res}
     if "a_priori" in short:
         short["a_priori"] = {k: v for k, v in short["a_priori"].items() if k != "per_snapshot"}
