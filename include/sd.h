@@ -6,8 +6,9 @@
  * written as the first-order system with the auxiliary gradient v = grad u
  * and mapped to the reference hexahedron (Lodato & Tonicello, section 2,
  * eqs. ns and ns:mapped/adj:f), on structured periodic hexahedral meshes:
- * uniform Cartesian ones, or (3-D diffusion) curvilinear elements given by
- * their node coordinates (sd_set_geometry).  The
+ * uniform Cartesian ones, or (3-D diffusion and Navier-Stokes, FP64)
+ * curvilinear elements given by their node coordinates (sd_set_geometry).
+ * The
  * auxiliary gradient is reconstructed either with the standard BR1-type
  * centred treatment (section 2.1: common solution eq. c:flux, gradient
  * eqs. w:e/v:e, common gradient eq. aux:v:int; five-element stencil in 1-D)
@@ -168,7 +169,14 @@ int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
 int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
 
 /* Curvilinear hexahedra (section 2.3: q = J u, G = S.F, H = S^T u with
- * S = adj(dx/dxi)) for a 3-D diffusion context in FP64.  nodes: HOST array
+ * S = adj(dx/dxi)) for a 3-D diffusion or Navier-Stokes context in FP64.
+ * Navier-Stokes (p <= 5): G_d = S_d . (F_c - F_v) at the flux points of
+ * family d; at a face the Roe flux along n = S_d / |S_d| times |S_d| (the
+ * Harten fix as on Cartesian meshes) minus S_d . F_v of the averaged
+ * solution and gradient; the gradient of every conservative variable is the
+ * auxiliary variable of the scalar case.  Diagnostics, sd_stable_dt, the
+ * closure and the interior penalty stay Cartesian-only on such a context
+ * (SD_EUNSUPPORTED).  nodes: HOST array
  * [ne][q+1][q+1][q+1][3] (copied), the coordinates of q + 1 equispaced
  * nodes per direction of every element (ends included, the first index
  * along zeta, the last along xi), q = 1 or 2; element e keeps its place in
@@ -180,7 +188,9 @@ int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
  * are preserved exactly when 2q <= p + 1.  Returns SD_EINVAL for a null
  * argument, q outside {1, 2} or an element whose det J is not positive at
  * a solution point (or, with the interior penalty on, at a face point);
- * SD_EUNSUPPORTED for other physics, dimensions or precisions; SD_ENOMEM /
+ * SD_EUNSUPPORTED for other physics, dimensions or precisions, for
+ * Navier-Stokes at p > 5 or with the interior penalty, and for a context
+ * whose closure is set; SD_ENOMEM /
  * SD_EHIP on device failures.  With eta_ip > 0 the penalty uses, at each
  * face point, 1/h = |S_d| max(J^-1 of the two sides) / 2 (on an affine
  * Cartesian element the 2/h_d of the box) and acts along n = S_d / |S_d|.

@@ -216,3 +216,225 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_rhs(const double *__rest
 }
 
 }  // namespace sd
+
+// ---------------------------------------------------------------------------
+// Navier-Stokes on curvilinear hexahedra (section 2.3, eqs. ns:mapped and
+// adj:f; fluxes of section 4.4), FP64.  The three kernels above for the five
+// conservative variables: traces T[e][f][v][q]; the gradient of every
+// variable at the solution points, VS[e][m*5 + v][pt], and at the faces,
+// VF[e][f][m*5 + v][q] (one-sided for the compact scheme); then
+// G_d = S_d . (F_c - F_v) at the interior flux points of family d, and at
+// the faces |S_d| Roe(U_L, U_R; S_d / |S_d|) - S_d . F_v(u_hat, v_hat)
+// (option (a)), and du/dt = -J^-1 sum_d D_d G_d.  One element per block,
+// LDS sized per n (dynamic).
+// ---------------------------------------------------------------------------
+namespace sd {
+
+constexpr int kCvnThreads = 256;
+
+template <int N>
+struct CvnGradSmem {
+  static constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF;
+  static constexpr int U = 0, T = U + 5 * NP, UH = T + 30 * NF, UF = UH + 30 * NF, V = UF + 15 * NL;
+  static constexpr int TOTAL = V + 15 * NP;   // doubles
+};
+template <int N>
+struct CvnRhsSmem {
+  static constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF;
+  static constexpr int V = 0, U = V + 15 * NP, TO = U + 5 * NP, TN = TO + 30 * NF, VH = TN + 30 * NF,
+                       G = VH + 90 * NF;
+  static constexpr int TOTAL = G + 15 * NL;
+};
+
+template <int N>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_traces(const double *__restrict__ U, double *__restrict__ T,
+                                                            const double *__restrict__ ops, long long ne) {
+  constexpr OpsLayout O = ops_layout(N);
+  constexpr int NP = N * N * N, NF = N * N;
+  const long long e = blockIdx.x;
+  if (e >= ne) return;
+  for (int t = threadIdx.x; t < 30 * NF; t += blockDim.x) {
+    const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF, d = f >> 1, s = f & 1;
+    const double *u = U + (e * 5 + v) * NP;
+    double acc = 0.0;
+    for (int c = 0; c < N; ++c) acc += ops[O.Lend + s * N + c] * u[cv_point<N>(d, q, c)];
+    T[e * 30 * NF + t] = acc;
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restrict__ U, const double *__restrict__ T,
+                                                          const double *__restrict__ Sf,
+                                                          const double *__restrict__ Jinv,
+                                                          const double *__restrict__ ops, KArgs a, int compact,
+                                                          double *__restrict__ VF, double *__restrict__ VS) {
+  using SM = CvnGradSmem<N>;
+  constexpr OpsLayout O = ops_layout(N);
+  constexpr int NP = SM::NP, NF = SM::NF, NL = SM::NL;
+  extern __shared__ double smem_cvn[];
+  double *su = smem_cvn + SM::U, *sT = smem_cvn + SM::T, *sUh = smem_cvn + SM::UH, *sUF = smem_cvn + SM::UF,
+         *sV = smem_cvn + SM::V;
+  const long long e = blockIdx.x;
+  if (e >= a.ne) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const double *ji = Jinv + e * NP;
+  const double *S = Sf + e * 9 * NL;
+  for (int t = tid; t < 5 * NP; t += nth) su[t] = U[e * 5 * NP + t];
+  for (int t = tid; t < 30 * NF; t += nth) {
+    const int f = t / (5 * NF), w = t % (5 * NF), d = f >> 1, s = f & 1;
+    const double own = T[e * 30 * NF + t];
+    const double oth = T[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
+    sT[t] = own;
+    sUh[t] = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+  }
+  __syncthreads();
+  // continuous solution of every variable at the flux points of every family
+  for (int t = tid; t < 15 * NL; t += nth) {
+    const int d = t / (5 * NL), w = t % (5 * NL), v = w / NL, l = w % NL, q = l / (N + 1), r = l % (N + 1);
+    double val;
+    if (r == 0) {
+      val = sUh[((2 * d) * 5 + v) * NF + q];
+    } else if (r == N) {
+      val = sUh[((2 * d + 1) * 5 + v) * NF + q];
+    } else {
+      val = 0.0;
+      for (int c = 0; c < N; ++c) val += ops[O.Lint + (r - 1) * N + c] * su[v * NP + cv_point<N>(d, q, c)];
+    }
+    sUF[t] = val;
+  }
+  __syncthreads();
+  // gradient of every variable at the solution points
+  for (int t = tid; t < 15 * NP; t += nth) {
+    const int mv = t / NP, pt = t % NP, m = mv / 5, v = mv % 5;
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      int q, c;
+      cv_line_of<N>(pt, d, q, c);
+      double dd = 0.0;
+      for (int r = 0; r <= N; ++r)
+        dd += ops[O.M + c * (N + 1) + r] *
+              (sUF[(d * 5 + v) * NL + q * (N + 1) + r] * S[((d * NF + q) * (N + 1) + r) * 3 + m]);
+      acc += dd;
+    }
+    const double g = ji[pt] * acc;
+    sV[t] = g;
+    VS[e * 15 * NP + t] = g;
+  }
+  __syncthreads();
+  // values at the faces: one-sided (compact: the family-d solution of face s
+  // keeps the own trace at the other face) or standard
+  for (int t = tid; t < 90 * NF; t += nth) {
+    const int f = t / (15 * NF), w = t % (15 * NF), mv = w / NF, q = w % NF, m = mv / 5, v = mv % 5;
+    const int d = f >> 1, s = f & 1;
+    double corr = 0.0;
+    int rend = 0;
+    if (compact) {
+      const int so = 1 - s;
+      rend = so == 0 ? 0 : N;
+      corr = (sT[((2 * d + so) * 5 + v) * NF + q] - sUh[((2 * d + so) * 5 + v) * NF + q]) *
+             S[((d * NF + q) * (N + 1) + rend) * 3 + m];
+    }
+    double acc = 0.0;
+    for (int c = 0; c < N; ++c) {
+      const int pt = cv_point<N>(d, q, c);
+      double g = sV[mv * NP + pt];
+      if (compact) g += ji[pt] * (ops[O.M + c * (N + 1) + rend] * corr);
+      acc += ops[O.Lend + s * N + c] * g;
+    }
+    VF[e * 90 * NF + t] = acc;
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_rhs(const double *__restrict__ U, const double *__restrict__ T,
+                                                         const double *__restrict__ VF,
+                                                         const double *__restrict__ VS,
+                                                         const double *__restrict__ Sf,
+                                                         const double *__restrict__ Jinv,
+                                                         const double *__restrict__ ops, KArgs a,
+                                                         double *__restrict__ dudt) {
+  using SM = CvnRhsSmem<N>;
+  constexpr OpsLayout O = ops_layout(N);
+  constexpr int NP = SM::NP, NF = SM::NF, NL = SM::NL;
+  extern __shared__ double smem_cvn[];
+  double *sV = smem_cvn + SM::V, *su = smem_cvn + SM::U, *sTo = smem_cvn + SM::TO, *sTn = smem_cvn + SM::TN,
+         *sVh = smem_cvn + SM::VH, *sG = smem_cvn + SM::G;
+  const long long e = blockIdx.x;
+  if (e >= a.ne) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const double *S = Sf + e * 9 * NL;
+  const double *ji = Jinv + e * NP;
+  for (int t = tid; t < 15 * NP; t += nth) sV[t] = VS[e * 15 * NP + t];
+  for (int t = tid; t < 5 * NP; t += nth) su[t] = U[e * 5 * NP + t];
+  for (int t = tid; t < 30 * NF; t += nth) {
+    const int f = t / (5 * NF), w = t % (5 * NF), d = f >> 1, s = f & 1;
+    sTo[t] = T[e * 30 * NF + t];
+    sTn[t] = T[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
+  }
+  for (int t = tid; t < 90 * NF; t += nth) {
+    const int f = t / (15 * NF), w = t % (15 * NF), d = f >> 1, s = f & 1;
+    const double own = VF[e * 90 * NF + t];
+    const double oth = VF[nbr(a, e, d, s) * 90 * NF + (2 * d + 1 - s) * 15 * NF + w];
+    sVh[t] = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+  }
+  __syncthreads();
+  // G_d at the flux points of family d: one item per (d, line, flux point)
+  const NsConst<double> c(a);
+  for (int t = tid; t < 3 * NL; t += nth) {
+    const int d = t / NL, l = t % NL, q = l / (N + 1), r = l % (N + 1);
+    const double *srow = S + ((d * NF + q) * (N + 1) + r) * 3;
+    const double sv[3] = {srow[0], srow[1], srow[2]};
+    double G[5];
+    if (r == 0 || r == N) {
+      const int s = r == 0 ? 0 : 1, f = 2 * d + s;
+      double UL[5], UR[5], Uh[5], Vh[15];
+      for (int v = 0; v < 5; ++v) {
+        const double own = sTo[(f * 5 + v) * NF + q], oth = sTn[(f * 5 + v) * NF + q];
+        UL[v] = s == 0 ? oth : own;
+        UR[v] = s == 0 ? own : oth;
+        Uh[v] = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+      }
+      for (int mv = 0; mv < 15; ++mv) Vh[mv] = sVh[(f * 15 + mv) * NF + q];
+      const double nrm = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+      const double nv[3] = {sv[0] / nrm, sv[1] / nrm, sv[2] / nrm};
+      double Fr[5], Fv[5];
+      ns_roe_dir(c, UL, UR, nv, Fr);
+      Prim<double> st = ns_prim(c, Uh);
+      ns_visc_dir(c, st, Vh, sv, Fv);
+      for (int v = 0; v < 5; ++v) G[v] = nrm * Fr[v] - Fv[v];
+    } else {
+      double Uf[5], Vf[15];
+      for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (int cc = 0; cc < N; ++cc) acc += ops[O.Lint + (r - 1) * N + cc] * su[v * NP + cv_point<N>(d, q, cc)];
+        Uf[v] = acc;
+      }
+      for (int mv = 0; mv < 15; ++mv) {
+        double acc = 0.0;
+        for (int cc = 0; cc < N; ++cc) acc += ops[O.Lint + (r - 1) * N + cc] * sV[mv * NP + cv_point<N>(d, q, cc)];
+        Vf[mv] = acc;
+      }
+      Prim<double> st = ns_prim(c, Uf);
+      double Fc[5], Fv[5];
+      ns_conv_dir(c, Uf, st, sv, Fc);
+      ns_visc_dir(c, st, Vf, sv, Fv);
+      for (int v = 0; v < 5; ++v) G[v] = Fc[v] - Fv[v];
+    }
+    for (int v = 0; v < 5; ++v) sG[(d * 5 + v) * NL + l] = G[v];
+  }
+  __syncthreads();
+  for (int t = tid; t < 5 * NP; t += nth) {
+    const int v = t / NP, pt = t % NP;
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      int q, cc;
+      cv_line_of<N>(pt, d, q, cc);
+      double dd = 0.0;
+      for (int r = 0; r <= N; ++r) dd += ops[O.M + cc * (N + 1) + r] * sG[(d * 5 + v) * NL + q * (N + 1) + r];
+      acc += dd;
+    }
+    dudt[e * 5 * NP + t] = -ji[pt] * acc;
+  }
+}
+
+}  // namespace sd

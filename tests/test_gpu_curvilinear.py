@@ -132,7 +132,8 @@ def test_curvilinear_argument_checks(torch_cuda):
     nel, p = (2, 2, 2), 2
     good = W.mesh_nodes(nel, *BOX, q=1)
     lo, hi = W.tgv_domain()
-    for kw in (dict(physics="ns", lo=lo, hi=hi), dict(physics="diffusion", precision="fp32", lo=lo, hi=hi)):
+    for kw in (dict(physics="ns", precision="fp32", lo=lo, hi=hi),
+               dict(physics="diffusion", precision="fp32", lo=lo, hi=hi)):
         sd = SD(nel, p, scheme="compact", **kw)
         with pytest.raises(SDError):
             sd.set_geometry(good)

@@ -1,0 +1,198 @@
+"""Curvilinear hexahedra for the compressible Navier-Stokes equations on the
+GPU (FP64) against the curvilinear reference (section 2.3 with the fluxes of
+section 4.4): right-hand sides on affine, rotated (full S) and curved meshes,
+ragged element counts, p = 1..5, both schemes; a 16^3 curved mesh (every
+value); RK4 and SSP-RK(5,4) steps; conservation; argument checks.
+
+Bar: per conserved variable, max(1e-12, 4 x the reference's one-ulp
+sensitivity), relative to that variable's largest residual.  The sensitivity
+is the larger change of the reference's RHS when every state value, or every
+node coordinate, moves by about one FP64 ulp: the library evaluates the
+metric terms from the nodes in its own order, so its S differs from the
+reference's by a few ulps, and at p = 5 on a curved mesh the momentum
+residual moves by ~2e-12 of its size for a one-ulp change of the nodes."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import curvilinear as C
+from oracle import oracle as O
+from oracle import ssprk
+from paper_2608_09615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+BOX = ((0.0, 0.0, 0.0), (2 * math.pi,) * 3)
+RE = 400.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(torch, nel, p, scheme, Xg, **kw):
+    from paper_2608_09615_amd import SD
+    print(f"[curv-ns] nel={nel} p={p} {scheme} q={Xg.shape[1] - 1}", flush=True)
+    lo, hi = W.tgv_domain()
+    sd = SD(nel, p, scheme=scheme, physics="ns", precision="fp64", lo=lo, hi=hi, Re=RE, **kw)
+    sd.set_geometry(Xg)
+    return sd
+
+
+def meshes(nel):
+    Q = np.array([[0.6, -0.8, 0.0], [0.48, 0.36, -0.8], [0.64, 0.48, 0.6]])
+    return {
+        "affine": W.mesh_nodes(nel, (0.0, 0.0, 0.0), (2.0, 4.0, 3.0), q=1),
+        "rotated": W.mesh_nodes(nel, (0.0, 0.0, 0.0), (2.0, 4.0, 3.0), q=1, rotation=Q),
+        "curved": W.mesh_nodes(nel, *BOX, q=2, displacement=W.periodic_wave_displacement(0.2)),
+    }
+
+
+def reference(U, nel, Xg, p, scheme):
+    """The reference's RHS and, per variable, its largest relative change
+    when every state value or every node coordinate moves by about one FP64
+    ulp."""
+    prm = O.make_params("ns", Re=RE)
+    Ro = C.rhs_ns(U, nel, Xg, p, scheme, prm)
+    rng = np.random.Generator(np.random.PCG64(1))
+    R2 = C.rhs_ns(U * (1.0 + 2.2e-16 * rng.uniform(-1, 1, U.shape)), nel, Xg, p, scheme, prm)
+    R3 = C.rhs_ns(U, nel, Xg * (1.0 + 2.2e-16 * rng.uniform(-1, 1, Xg.shape)), p, scheme, prm)
+    sens = [max(np.abs(R2[:, v] - Ro[:, v]).max(), np.abs(R3[:, v] - Ro[:, v]).max()) / np.abs(Ro[:, v]).max()
+            for v in range(5)]
+    return Ro, sens
+
+
+def check(R, Ro, sens, what):
+    for v in range(5):
+        err = np.abs(R[:, v] - Ro[:, v]).max() / np.abs(Ro[:, v]).max()
+        bar = max(1e-12, 4 * sens[v])
+        print(f"  {what} var {v}: {err:.2e} (bar {bar:.1e})", flush=True)
+        assert err < bar, (what, v, err, sens[v])
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_curvilinear_ns_rhs_parity(torch_cuda, scheme, p):
+    for nel in ((3, 2, 4), (1, 3, 2)):
+        U = W.perturbed_tgv_state(nel, p, seed=20 + p, noise=1e-2)
+        for name, Xg in meshes(nel).items():
+            sd = make(torch_cuda, nel, p, scheme, Xg)
+            R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+            sd.close()
+            Ro, sens = reference(U, nel, Xg, p, scheme)
+            check(R, Ro, sens, f"{name} {nel}")
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_curvilinear_ns_near_sonic_faces(torch_cuda, scheme):
+    """The transonic-jet state (normal velocities through the sound speed)
+    on the curved mesh: Harten's fix acts on faces of every family."""
+    nel, p = (4, 3, 4), 3
+    U = W.transonic_jet_state(nel, p, seed=2)
+    Xg = meshes(nel)["curved"]
+    sd = make(torch_cuda, nel, p, scheme, Xg)
+    R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+    sd.close()
+    Ro, sens = reference(U, nel, Xg, p, scheme)
+    check(R, Ro, sens, "transonic jet")
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_curvilinear_ns_16cubed(torch_cuda, scheme):
+    """16^3 degree-2 elements at p = 3 (262 144 solution points, 5 variables),
+    every value."""
+    nel, p = (16, 16, 16), 3
+    Xg = W.mesh_nodes(nel, *BOX, q=2, displacement=W.periodic_wave_displacement(0.3))
+    U = W.perturbed_tgv_state(nel, p, seed=6, noise=1e-3)
+    sd = make(torch_cuda, nel, p, scheme, Xg)
+    R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+    sd.close()
+    Ro, sens = reference(U, nel, Xg, p, scheme)
+    check(R, Ro, sens, f"16^3 curved {scheme}")
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "ssprk54"])
+def test_curvilinear_ns_time_steps(torch_cuda, integrator):
+    nel, p, dt = (3, 3, 2), 3, 2e-3
+    Xg = meshes(nel)["curved"]
+    U0 = W.perturbed_tgv_state(nel, p, seed=13, noise=1e-2)
+    sd = make(torch_cuda, nel, p, "compact", Xg, integrator=integrator)
+    u = torch_cuda.from_numpy(U0.copy()).to("cuda")
+    for _ in range(2):
+        sd.rk_step(u, dt)
+    got = u.cpu().numpy()
+    sd.close()
+    prm = O.make_params("ns", Re=RE)
+    f = lambda v: C.rhs_ns(v, nel, Xg, p, "compact", prm)
+    if integrator == "ssprk54":
+        ref = ssprk.integrate(f, U0, dt, 2)
+    else:
+        ref = U0
+        for _ in range(2):
+            k1 = f(ref)
+            k2 = f(ref + 0.5 * dt * k1)
+            k3 = f(ref + 0.5 * dt * k2)
+            k4 = f(ref + dt * k3)
+            ref = ref + dt / 6.0 * (((k1 + 2.0 * k2) + 2.0 * k3) + k4)
+    # the RHS's own rounding floor (state and node coordinates) carries over
+    # to the change it makes
+    _, sens = reference(U0, nel, Xg, p, "compact")
+    for v in range(5):
+        change = np.abs(ref[:, v] - U0[:, v]).max()
+        err = np.abs(got[:, v] - ref[:, v]).max() / change
+        # the stage sums round at the size of the state itself
+        floor = 2 * 10 * np.finfo(np.float64).eps * np.abs(U0[:, v]).max() / change
+        print(f"{integrator} var {v}: {err:.2e} of the change (floor {floor:.1e}, rhs {sens[v]:.1e})")
+        assert err < max(1e-12, floor, 4 * sens[v]), (v, err, floor, sens[v])
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+def test_curvilinear_ns_conserves(torch_cuda, scheme):
+    """sum_e sum_q w_q J dU/dt = 0 for every conserved variable on the curved
+    periodic mesh (the two sides of a face share the same flux), to the
+    rounding that the reference's own FP64 evaluation shows: the weighted
+    divergence rows telescope only up to rounding, which leaves the momentum
+    sums at ~5e-14 of sum |w J R| there (mass and energy at ~4e-16)."""
+    nel, p = (3, 4, 3), 3
+    Xg = meshes(nel)["curved"]
+    U = W.perturbed_tgv_state(nel, p, seed=4, noise=1e-2)
+    sd = make(torch_cuda, nel, p, scheme, Xg)
+    R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+    sd.close()
+    Ro = C.rhs_ns(U, nel, Xg, p, scheme, O.make_params("ns", Re=RE))
+    _, w = W.gl_nodes(p + 1)
+    W3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    _, detJ = C.metrics(Xg, p)
+    for v in range(5):
+        tot = np.sum(W3[None] * detJ * R[:, v])
+        mag = np.sum(W3[None] * detJ * np.abs(R[:, v]))
+        ref = abs(np.sum(W3[None] * detJ * Ro[:, v]))
+        print(f"  var {v}: {tot / mag:.1e} (reference {ref / mag:.1e})")
+        assert abs(tot) < max(1e-13 * mag, 10 * ref), (v, tot, ref, mag)
+
+
+def test_curvilinear_ns_argument_checks(torch_cuda):
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd.sd import SDError
+    lo, hi = W.tgv_domain()
+    good = W.mesh_nodes((2, 2, 2), *BOX, q=1)
+    for p, kw in ((2, dict(precision="fp32")), (2, dict(precision="fp32mfma")), (2, dict(eta_ip=0.4)),
+                  (6, dict())):
+        sd = SD((2, 2, 2), p, scheme="compact", physics="ns", lo=lo, hi=hi, **kw)
+        with pytest.raises(SDError):
+            sd.set_geometry(good)
+        sd.close()
+    sd = make(torch_cuda, (2, 2, 2), 2, "compact", good)
+    U = W.perturbed_tgv_state((2, 2, 2), 2, seed=1, noise=1e-2)
+    u = torch_cuda.from_numpy(U).to("cuda")
+    # the diagnostics' quadrature is the Cartesian element's
+    with pytest.raises(SDError):
+        sd.diagnostics(u)
+    R = sd.rhs(u).cpu().numpy()
+    sd.close()
+    Ro, sens = reference(U, (2, 2, 2), good, 2, "compact")
+    check(R, Ro, sens, "after the rejected calls")
