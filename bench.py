@@ -67,7 +67,8 @@ def parse():
                     help="elements per direction of the curvilinear diffusion workload (0: skip it)")
     ap.add_argument("--closure-nel", type=int, default=16,
                     help="elements per direction of the learned-closure timing (0: skip it)")
-    ap.add_argument("--only", choices=["bloch", "curvilinear", "closure"], default=None,
+    ap.add_argument("--only", choices=["bloch", "curvilinear", "curvilinear_ns", "closure", "training"],
+                    default=None,
                     help="time only that workload and print its record")
     return ap.parse_args()
 
@@ -80,7 +81,7 @@ TRAFFIC_SOURCES = ["sd_ns_kernel.h", "sd_internal.h", "sd_physics.h", "sd_dispat
 PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
-CURV_TRAFFIC_SOURCES = ["sd_curv_kernel.h", "sd_curv.inc", "sd_internal.h", "sd_operators.cpp"]
+CURV_TRAFFIC_SOURCES = ["sd_curv_kernel.h", "sd_curv.inc", "sd_internal.h", "sd_physics.h", "sd_operators.cpp"]
 
 
 # the sources of k_closure_fused and its launch
@@ -315,13 +316,14 @@ def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
                          "kernels": "k_bloch_lane_cm (combined mode)"}}
 
 
-def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20):
-    """Linear diffusion on curvilinear hexahedra (degree-2 elements of a
+def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20, physics="diffusion"):
+    """Right-hand side on curvilinear hexahedra (degree-2 elements of a
     periodic box moved by a smooth wave of amplitude 0.3), FP64, one RHS per
-    step.  Roofline: HBM, with the algorithmic bytes per element the state
-    in and the RHS out (2 x 8 n^3) plus the metric terms the kernels must
-    read (S rows at 3 (n+1) n^2 flux points, 1/det J at n^3 points: 8 (9 (n+1)
-    n^2 + n^3))."""
+    step: linear diffusion of a smooth field, or the Navier-Stokes equations
+    of the Taylor-Green state at Re = 1600.  Roofline: HBM, with the
+    algorithmic bytes per element the state in and the RHS out
+    (2 x 8 nv n^3) plus the metric terms the kernels must read (S rows at
+    3 (n+1) n^2 flux points, 1/det J at n^3 points: 8 (9 (n+1) n^2 + n^3))."""
     import numpy as np
     from paper_2608_09615_amd import SD
     from paper_2608_09615_amd import workloads as W
@@ -330,11 +332,22 @@ def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20):
     n = p + 1
     box = ((0.0, 0.0, 0.0), (2 * math.pi,) * 3)
     Xg = W.mesh_nodes(nel, *box, q=2, displacement=W.periodic_wave_displacement(0.3))
-    sd = SD(nel, p, scheme=scheme, physics="diffusion", lo=[0.0] * 3, hi=[1.0] * 3)
+    if physics == "ns":
+        nv = 5
+        lo, hi = W.tgv_domain()
+        sd = SD(nel, p, scheme=scheme, physics="ns", lo=lo, hi=hi, Re=1600.0, Ma=0.1, Pr=0.71)
+        u = torch.from_numpy(W.perturbed_tgv_state(nel, p, seed=0)).to("cuda")
+        what = "compressible Navier-Stokes (Taylor-Green state, Re=1600, Ma=0.1)"
+        kernels = "k_cvn_traces + k_cvn_grad + k_cvn_face"
+    else:
+        nv = 1
+        sd = SD(nel, p, scheme=scheme, physics="diffusion", lo=[0.0] * 3, hi=[1.0] * 3)
+        x = W.map_points(Xg, p)
+        u = torch.from_numpy(np.ascontiguousarray((np.sin(x[..., 0]) * np.sin(x[..., 1]) * np.sin(x[..., 2]))[:, None]))
+        u = u.to("cuda")
+        what = "linear diffusion"
+        kernels = "k_cv_traces + k_cv_grad + k_cv_face"
     sd.set_geometry(Xg)
-    x = W.map_points(Xg, p)
-    u = torch.from_numpy(np.ascontiguousarray((np.sin(x[..., 0]) * np.sin(x[..., 1]) * np.sin(x[..., 2]))[:, None]))
-    u = u.to("cuda")
     out = torch.empty_like(u)
     for _ in range(3):
         sd.rhs(u, out)
@@ -349,14 +362,14 @@ def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20):
     ms = e0.elapsed_time(e1) / reps
     sd.close()
     dof = N ** 3 * n ** 3
-    bytes_el = 16.0 * n ** 3 + 8.0 * (9 * (n + 1) * n * n + n ** 3)
+    bytes_el = 16.0 * nv * n ** 3 + 8.0 * (9 * (n + 1) * n * n + n ** 3)
     gbs = bytes_el * N ** 3 / (ms * 1e-3) / 1e9
-    return {"config": f"linear diffusion, {N}^3 degree-2 hexahedra (periodic box, wave displacement 0.3), "
+    return {"config": f"{what}, {N}^3 degree-2 hexahedra (periodic box, wave displacement 0.3), "
                       f"p={p} {scheme}, FP64",
-            "gdofs_per_rhs": dof / ms / 1e6, "ms_per_rhs": ms,
+            "gdofs_per_rhs": dof / ms / 1e6, "ms_per_rhs": ms, "variables": nv,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": curv_traffic(N, p, scheme),
-                         "traffic_unit": "B per RHS", "kernels": "k_cv_traces + k_cv_grad + k_cv_rhs"}}
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": curv_traffic(N, p, scheme, physics),
+                         "traffic_unit": "B per RHS", "kernels": kernels}}
 
 
 def closure_bench(torch, args, p=3, hidden=128, reps=200):
@@ -413,6 +426,49 @@ def closure_bench(torch, args, p=3, hidden=128, reps=200):
                          "duration": "closure_us (RHS time with the closure minus without)"}}
 
 
+def training_bench(torch, args, p=3, hidden=128, batch=1024, steps=200):
+    """One training step of the closure network (5 n^3 -> hidden -> hidden ->
+    5 n^3, GELU) on seeded random data, all on the library's kernels:
+    forward (BF16 matrix cores), MSE, backward (FP32 matrix cores) and Adam,
+    batch 1024, timed over ``steps`` steps with HIP events (host launch gaps
+    included).  Algorithmic flops per step: the forward products
+    2 B (n_in h + h h + h n_out), the weight gradients as many, and the
+    products back to the two hidden layers' inputs 2 B (n_out h + h h)."""
+    import numpy as np
+    from paper_2608_09615_amd.sd import Mlp, mse
+    from paper_2608_09615_amd.closure import init_params_flat
+    nve = 5 * (p + 1) ** 3
+    rng = np.random.Generator(np.random.PCG64(3))
+    X = torch.from_numpy(rng.normal(size=(batch, nve)).astype(np.float32)).to("cuda")
+    T = torch.from_numpy(rng.normal(size=(batch, nve)).astype(np.float32)).to("cuda")
+    net = Mlp(nve, hidden, nve, P=torch.from_numpy(init_params_flat(nve, hidden, nve, 0)).to("cuda"))
+    dY = torch.empty((batch, nve), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        Y = net.forward(X)
+        mse(Y, T, dY, loss)
+        net.backward(dY)
+        net.adam(1e-4)
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / steps * 1e3
+    fwd = 2.0 * batch * (nve * hidden + hidden * hidden + hidden * nve)
+    flop = 2 * fwd + 2.0 * batch * (nve * hidden + hidden * hidden)
+    tf = flop / (us * 1e-6) / 1e12
+    return {"config": f"closure network {nve}-{hidden}-{hidden}-{nve} GELU, batch {batch}, forward + MSE + "
+                      f"backward + Adam", "us_per_step": us, "steps_per_s": 1e6 / us, "flop_per_step": flop,
+            "tflops": tf, "frac_fp32_mfma": tf / PEAK_FP32_MFMA_TFLOPS}
+
+
 def closure_traffic(N, p, hidden):
     """HBM bytes per k_closure_fused launch from the committed counter
     record, or None for another workload or once a source it is keyed to
@@ -427,10 +483,11 @@ def closure_traffic(N, p, hidden):
     return rec["bytes_per_launch"]
 
 
-def curv_traffic(N, p, scheme):
+def curv_traffic(N, p, scheme, physics="diffusion"):
     """HBM bytes per curvilinear RHS from the committed counter record, or
     None for another workload or once a source it is keyed to has changed."""
-    path = os.path.join(ROOT, "profiles", "curv_traffic_32cubed_p3.json")
+    name = "curv_traffic_32cubed_p3.json" if physics == "diffusion" else "curv_ns_traffic_32cubed_p3.json"
+    path = os.path.join(ROOT, "profiles", name)
     if not (N == 32 and p == 3 and scheme == "compact" and os.path.exists(path)):
         return None
     with open(path) as f:
@@ -463,21 +520,6 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.only == "bloch":
-        print(json.dumps({"bloch": bloch_bench(torch, args)}), flush=True)
-        return
-    if args.only == "curvilinear":
-        print(json.dumps({"curvilinear": curvilinear_bench(torch, args)}), flush=True)
-        return
-    if args.only == "closure":
-        print(json.dumps({"closure": closure_bench(torch, args)}), flush=True)
-        return
-    nel = (args.nel,) * 3
-    U0 = W.tgv_state(nel, args.p)
-    h = 2 * math.pi / args.nel
-    c0 = math.sqrt(1.4 * (1.0 / 1.4 / 0.01) / 1.0)
-    dt = 0.3 * h / ((args.p + 1) * (1.0 + c0))
-    print(f"bench: TGV {nel} p={args.p} {args.scheme} dt={dt:.3e}", file=sys.stderr, flush=True)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -485,6 +527,27 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: copy probe {args.copy_probe_mib} MiB", file=sys.stderr, flush=True)
         del src, dst
+    if args.only == "bloch":
+        print(json.dumps({"bloch": bloch_bench(torch, args)}), flush=True)
+        return
+    if args.only == "curvilinear":
+        print(json.dumps({"curvilinear": curvilinear_bench(torch, args)}), flush=True)
+        return
+    if args.only == "curvilinear_ns":
+        print(json.dumps({"curvilinear_ns": curvilinear_bench(torch, args, physics="ns")}), flush=True)
+        return
+    if args.only == "closure":
+        print(json.dumps({"closure": closure_bench(torch, args)}), flush=True)
+        return
+    if args.only == "training":
+        print(json.dumps({"closure_training": training_bench(torch, args)}), flush=True)
+        return
+    nel = (args.nel,) * 3
+    U0 = W.tgv_state(nel, args.p)
+    h = 2 * math.pi / args.nel
+    c0 = math.sqrt(1.4 * (1.0 / 1.4 / 0.01) / 1.0)
+    dt = 0.3 * h / ((args.p + 1) * (1.0 + c0))
+    print(f"bench: TGV {nel} p={args.p} {args.scheme} dt={dt:.3e}", file=sys.stderr, flush=True)
     precs = args.precisions.split(",")
     r32 = run_path(torch, W, args, "fp32", U0, dt) if "fp32" in precs else None
     if r32:
@@ -561,8 +624,10 @@ def main():
         rec["bloch"] = bloch_bench(torch, args)
     if args.curv_nel > 0:
         rec["curvilinear"] = curvilinear_bench(torch, args)
+        rec["curvilinear_ns"] = curvilinear_bench(torch, args, physics="ns")
     if args.closure_nel > 0:
         rec["closure"] = closure_bench(torch, args)
+        rec["closure_training"] = training_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0, fp64_rhs(torch, args, U0))
     print(json.dumps(rec), flush=True)

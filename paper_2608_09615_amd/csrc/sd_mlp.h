@@ -1,6 +1,7 @@
 // Kernels of the learned closure: a dense MLP with exact-erf GELU, forward on
 // BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation),
-// backward in FP32, MSE, Adam; and the fine-to-coarse L2 projection filter.
+// backward products on FP32 matrix cores (v_mfma_f32_16x16x4f32), MSE, Adam;
+// and the fine-to-coarse L2 projection filter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,56 +67,56 @@ __global__ void __launch_bounds__(256) k_dense_fwd(const uint16_t *__restrict__ 
   }
 }
 
-// C [M][N] = sum_k A(m, k) B(k, n) in FP32 with strided operands; 32x32
-// output tile per block of 256 threads, 2x2 outputs per thread.
-template <typename TA, typename TB>
+// C [M][N] = sum_k A(m, k) B(k, n) with strided operands on the FP32 matrix
+// cores (v_mfma_f32_16x16x4f32: lane l supplies A(l%16, k0 + l/16) and
+// B(k0 + l/16, l%16) and receives C[4(l/16)+j][l%16]), FP32 products and
+// sums.  One 16x16 tile of C per block of kGemmWaves wavefronts: wave w sums
+// the w-th contiguous quarter of the k range and the partial tiles are added
+// through LDS in wave order (a fixed order).  With GELU_BWD the tile is
+// multiplied by gelu'(Z[m][n]) on the way out (the activation's backward).
+template <typename TA>
 __device__ __forceinline__ float ld_as_f32(const TA *p) {
   if constexpr (sizeof(TA) == 2) return from_bf16(*reinterpret_cast<const uint16_t *>(p));
   else return *p;
 }
 
-template <typename TA, typename TB>
-__global__ void __launch_bounds__(256) k_gemm_f32(int M, int N, int K, const TA *__restrict__ A, long long sam,
-                                                  long long sak, const TB *__restrict__ B, long long sbk,
-                                                  long long sbn, float *__restrict__ C) {
-  __shared__ float As[32][33];
-  __shared__ float Bs[32][33];
-  const int tid = threadIdx.x;
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
-  const int ty = tid / 16, tx = tid % 16;
-  float c00 = 0.f, c01 = 0.f, c10 = 0.f, c11 = 0.f;
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    for (int idx = tid; idx < 1024; idx += 256) {
-      // fast index along the unit-stride dimension of each operand
-      int i, kk;
-      if (sam == 1) { i = idx % 32; kk = idx / 32; } else { kk = idx % 32; i = idx / 32; }
-      int m = m0 + i, k = k0 + kk;
-      As[i][kk] = (m < M && k < K) ? ld_as_f32<TA, TB>(A + m * sam + k * sak) : 0.f;
-      int jj, kb;
-      if (sbn == 1) { jj = idx % 32; kb = idx / 32; } else { kb = idx % 32; jj = idx / 32; }
-      int n = n0 + jj, k2 = k0 + kb;
-      Bs[kb][jj] = (n < N && k2 < K) ? ld_as_f32<TB, TA>(B + k2 * sbk + n * sbn) : 0.f;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      float a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
-      float b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
-      c00 += a0 * b0; c01 += a0 * b1; c10 += a1 * b0; c11 += a1 * b1;
-    }
-    __syncthreads();
-  }
-  int m = m0 + 2 * ty, n = n0 + 2 * tx;
-  if (m < M && n < N) C[(long long)m * N + n] = c00;
-  if (m < M && n + 1 < N) C[(long long)m * N + n + 1] = c01;
-  if (m + 1 < M && n < N) C[(long long)(m + 1) * N + n] = c10;
-  if (m + 1 < M && n + 1 < N) C[(long long)(m + 1) * N + n + 1] = c11;
-}
+constexpr int kGemmWaves = 4;
 
-// g <- g * gelu'(z)
-__global__ void k_gelu_bwd(float *__restrict__ g, const float *__restrict__ z, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) g[i] *= gelu_prime_f(z[i]);
+template <typename TA, typename TB, bool GELU_BWD>
+__global__ void __launch_bounds__(64 * kGemmWaves) k_gemm_mfma(int M, int N, int K, const TA *__restrict__ A,
+                                                               long long sam, long long sak,
+                                                               const TB *__restrict__ B, long long sbk,
+                                                               long long sbn, const float *__restrict__ Z,
+                                                               float *__restrict__ C) {
+  __shared__ float red[kGemmWaves - 1][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const long long m = (long long)blockIdx.y * 16 + r, n = (long long)blockIdx.x * 16 + r;
+  const int kc = ((K + 4 * kGemmWaves - 1) / (4 * kGemmWaves)) * 4;
+  const int kb = w * kc, ke = min(K, kb + kc);
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const long long k = k0 + kq;
+    const float a = (m < M && k < ke) ? ld_as_f32(A + m * sam + k * sak) : 0.f;
+    const float b = (n < N && k < ke) ? ld_as_f32(B + k * sbk + n * sbn) : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  if (w > 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[w - 1][j][lane] = acc[j];
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float v = acc[j];
+    for (int ww = 0; ww < kGemmWaves - 1; ++ww) v += red[ww][j][lane];
+    const long long mo = (long long)blockIdx.y * 16 + 4 * kq + j;
+    if (mo < M && n < N) {
+      if constexpr (GELU_BWD) v *= gelu_prime_f(Z[mo * N + n]);
+      C[mo * N + n] = v;
+    }
+  }
 }
 
 // out[n] = sum_b x[b][n], one thread per column, fixed order
