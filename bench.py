@@ -64,7 +64,9 @@ def parse():
     ap.add_argument("--bloch-theta", type=int, default=1 << 16,
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
     ap.add_argument("--curv-nel", type=int, default=32,
-                    help="elements per direction of the curvilinear diffusion workload (0: skip it)")
+                    help="elements per direction of the curvilinear workloads (0: skip them)")
+    ap.add_argument("--curv-p", type=int, default=3, help="degree of the curvilinear workloads")
+    ap.add_argument("--curv-scheme", default="compact", choices=["compact", "br1"])
     ap.add_argument("--closure-nel", type=int, default=16,
                     help="elements per direction of the learned-closure timing (0: skip it)")
     ap.add_argument("--only", choices=["bloch", "curvilinear", "curvilinear_ns", "closure", "training"],
@@ -316,7 +318,7 @@ def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
                          "kernels": "k_bloch_lane_cm (combined mode)"}}
 
 
-def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20, physics="diffusion"):
+def curvilinear_bench(torch, args, reps=20, physics="diffusion"):
     """Right-hand side on curvilinear hexahedra (degree-2 elements of a
     periodic box moved by a smooth wave of amplitude 0.3), FP64, one RHS per
     step: linear diffusion of a smooth field, or the Navier-Stokes equations
@@ -327,7 +329,7 @@ def curvilinear_bench(torch, args, p=3, scheme="compact", reps=20, physics="diff
     import numpy as np
     from paper_2608_09615_amd import SD
     from paper_2608_09615_amd import workloads as W
-    N = args.curv_nel
+    N, p, scheme = args.curv_nel, args.curv_p, args.curv_scheme
     nel = (N,) * 3
     n = p + 1
     box = ((0.0, 0.0, 0.0), (2 * math.pi,) * 3)
@@ -429,7 +431,7 @@ def closure_bench(torch, args, p=3, hidden=128, reps=200):
 def training_bench(torch, args, p=3, hidden=128, batch=1024, steps=200):
     """One training step of the closure network (5 n^3 -> hidden -> hidden ->
     5 n^3, GELU) on seeded random data, all on the library's kernels:
-    forward (BF16 matrix cores), MSE, backward (FP32 matrix cores) and Adam,
+    forward (BF16 matrix cores), MSE gradient, backward (FP32 matrix cores) and Adam,
     batch 1024, timed over ``steps`` steps with HIP events (host launch gaps
     included).  Algorithmic flops per step: the forward products
     2 B (n_in h + h h + h n_out), the weight gradients as many, and the
@@ -443,11 +445,11 @@ def training_bench(torch, args, p=3, hidden=128, batch=1024, steps=200):
     T = torch.from_numpy(rng.normal(size=(batch, nve)).astype(np.float32)).to("cuda")
     net = Mlp(nve, hidden, nve, P=torch.from_numpy(init_params_flat(nve, hidden, nve, 0)).to("cuda"))
     dY = torch.empty((batch, nve), dtype=torch.float32, device="cuda")
-    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
 
     def step():
+        # the loss itself is reduced only when reported (as in the training loop)
         Y = net.forward(X)
-        mse(Y, T, dY, loss)
+        mse(Y, T, dY, None)
         net.backward(dY)
         net.adam(1e-4)
     for _ in range(5):

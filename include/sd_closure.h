@@ -63,14 +63,16 @@ int sd_mlp_forward_noalloc(const sd_mlp_shape *shape, const float *P, const uint
 
 /* Grad [param_count] = d(sum dY . Y)/dP for the forward pass whose
  * activations are in work (weights as their BF16 values, the roundings of
- * the forward pass treated as fixed); products in FP32. */
+ * the forward pass treated as fixed); products in FP32 on the FP32 matrix
+ * cores, every sum in a fixed order. */
 int sd_mlp_backward(const sd_mlp_shape *shape, const uint16_t *Wb, void *work, const float *dY, int batch,
                     float *grad, void *stream);
 
 /* Weighted mean square error of Y against T, both [rows][cols]:
  *     loss = sum_r w[r] sum_c (Y - T)^2 / (rows cols),  dY = 2 w[r] (Y - T) / (rows cols),
  * with w [rows] per-row weights (NULL = all ones); the loss goes to *loss
- * (device FP64 scalar), reduced in a fixed order. */
+ * (device FP64 scalar), reduced in a fixed order, or is not computed when
+ * loss is NULL (dY alone). */
 int sd_mse(const float *Y, const float *T, const float *w, long long rows, int cols, float *dY, double *loss,
            void *stream);
 

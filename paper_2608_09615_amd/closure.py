@@ -264,10 +264,11 @@ def fit(torch, Xn, Tn, hidden=128, iters=3000, batch=1024, lr=1e-3, seed=0, weig
         sl = slice(b * batch, (b + 1) * batch)
         xb, tb = Xs[sl], Ts[sl]
         Y = net.forward(xb)
-        mse(Y, tb, dY[:xb.shape[0]], loss, w=None if Ws is None else Ws[sl])
+        report = it % 1000 == 0 or it == iters - 1
+        mse(Y, tb, dY[:xb.shape[0]], loss if report else None, w=None if Ws is None else Ws[sl])
         net.backward(dY[:xb.shape[0]])
         net.adam(lr * (0.1 ** (it / iters)))
-        if it % 1000 == 0 or it == iters - 1:
+        if report:
             losses.append((it, loss.item()))
             log(f"closure: iter {it} loss {losses[-1][1]:.4e} ({time.perf_counter() - t0:.1f} s)")
     return net, losses

@@ -259,6 +259,105 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_face(const double *__res
 // ---------------------------------------------------------------------------
 namespace sd {
 
+// Fluxes along a direction vector s (curvilinear elements: the flux through
+// the rows of the adjugate S): F . s = sum_m s_m F e_m, with F_c(U0) . s
+// removed as above.
+template <typename R>
+__device__ __forceinline__ void ns_conv_dir(const NsConst<R> &c, const R *U, const Prim<R> &st, const R *sv, R *F) {
+  const R us = st.u[0] * sv[0] + st.u[1] * sv[1] + st.u[2] * sv[2];
+  F[0] = U[1] * sv[0] + U[2] * sv[1] + U[3] * sv[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[1 + i] = U[1 + i] * us + st.dp * sv[i];
+  F[4] = (st.rhoE + st.p) * us;
+}
+
+// F_v . s from the state and the conservative gradient G[m*5 + v]
+template <typename R>
+__device__ __forceinline__ void ns_visc_dir(const NsConst<R> &c, const Prim<R> &st, const R *G, const R *sv, R *F) {
+  R E = st.rhoE * st.inv;
+  R du[3][3], dT[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    R drho = G[m * 5 + 0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) du[i][m] = (G[m * 5 + 1 + i] - st.u[i] * drho) * st.inv;
+    R dE = (G[m * 5 + 4] - E * drho) * st.inv;
+    dT[m] = c.gm1 * (dE - (st.u[0] * du[0][m] + st.u[1] * du[1][m] + st.u[2] * du[2][m]));
+  }
+  R T = st.p * st.inv;
+  R mu = c.mu0;
+  if (c.suth) {
+    R th = T * c.T0inv;
+    mu = c.mu0 * th * fsqrt(th) * c.onepS * frcp(th + c.S);
+  }
+  const R lam = c.lam_over_mu * mu, kappa = c.cp_over_pr * mu;
+  const R div = du[0][0] + du[1][1] + du[2][2];
+  R ts[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    R acc = lam * div * sv[i];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc += mu * (du[i][m] + du[m][i]) * sv[m];
+    ts[i] = acc;
+  }
+  F[0] = R(0);
+  F[1] = ts[0];
+  F[2] = ts[1];
+  F[3] = ts[2];
+  F[4] = st.u[0] * ts[0] + st.u[1] * ts[1] + st.u[2] * ts[2] + kappa * (dT[0] * sv[0] + dT[1] * sv[1] + dT[2] * sv[2]);
+}
+
+// Roe flux along the unit normal n with Harten's fix on the acoustic waves
+// (the axis version above with u_d -> u . n and the tangential velocity jump
+// du - (du . n) n), minus F_c(U0) . n.
+template <typename R>
+__device__ __forceinline__ void ns_roe_dir(const NsConst<R> &c, const R *UL, const R *UR, const R *n, R *F) {
+  Prim<R> L = ns_prim(c, UL), Rr = ns_prim(c, UR);
+  R FL[5], FR[5];
+  ns_conv_dir(c, UL, L, n, FL);
+  ns_conv_dir(c, UR, Rr, n, FR);
+  R sL = fsqrt(L.rho), sR = fsqrt(Rr.rho);
+  R wsum = frcp(sL + sR);
+  R HL = (L.rhoE + L.p) * L.inv, HR = (Rr.rhoE + Rr.p) * Rr.inv;
+  R ut[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ut[i] = (sL * L.u[i] + sR * Rr.u[i]) * wsum;
+  R Ht = (sL * HL + sR * HR) * wsum;
+  R rt = sL * sR;
+  R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  R c2 = c.gm1 * (Ht - R(0.5) * q2);
+  R cs = fsqrt(c2);
+  R un = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+  R du[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) du[i] = Rr.u[i] - L.u[i];
+  R drho = Rr.rho - L.rho, dpj = Rr.dp - L.dp, dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  R ic2 = frcp(c2);
+  R inv2c2 = R(0.5) * ic2;
+  R a1 = (dpj - rt * cs * dun) * inv2c2;
+  R a5 = (dpj + rt * cs * dun) * inv2c2;
+  R a2 = drho - dpj * ic2;
+  R l1 = fabs(un - cs), l2 = fabs(un), l5 = fabs(un + cs);
+  R delta = c.efix * (l2 + cs);
+  if (delta > R(0)) {
+    R i2d = R(0.5) * frcp(delta);
+    if (l1 < delta) l1 = (l1 * l1 + delta * delta) * i2d;
+    if (l5 < delta) l5 = (l5 * l5 + delta * delta) * i2d;
+  }
+  R dut[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dut[i] = du[i] - dun * n[i];
+  R w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2, ws = l2 * rt;
+  R D[5];
+  D[0] = w1 + w2 + w5;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) D[1 + i] = (w1 + w5 + w2) * ut[i] + ws * dut[i] + (w5 - w1) * cs * n[i];
+  D[4] = w1 * (Ht - cs * un) + w5 * (Ht + cs * un) + w2 * R(0.5) * q2 +
+         ws * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) F[k] = R(0.5) * (FL[k] + FR[k]) - R(0.5) * D[k];
+}
+
 constexpr int kCvnThreads = 256;
 
 template <int N>
@@ -286,6 +385,30 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_traces(const double *__rest
 __device__ __forceinline__ double cvn_hat(const double *sT, const double *sTn, int f, int idx) {
   const double own = sT[idx], oth = sTn[idx];
   return (f & 1) == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+}
+
+// G_d = S_d . (F_c - F_v) at interior flux point w of family d (item t)
+template <int N>
+__device__ __forceinline__ void cvn_interior_item(const NsConst<double> &c, const double *__restrict__ ops,
+                                                  const double *sS, const double *sUF, const double *sV, double *sG,
+                                                  int t) {
+  constexpr OpsLayout O = ops_layout(N);
+  constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF, NI = (N - 1) * NF;
+  const int d = t / NI, w = t % NI, q = w / (N - 1), r = 1 + w % (N - 1);
+  const double *srow = sS + ((d * NF + q) * (N + 1) + r) * 3;
+  const double sv[3] = {srow[0], srow[1], srow[2]};
+  double Uf[5], Vf[15];
+  for (int v = 0; v < 5; ++v) Uf[v] = sUF[(d * 5 + v) * NL + q * (N + 1) + r];
+  for (int mv = 0; mv < 15; ++mv) {
+    double acc = 0.0;
+    for (int cc = 0; cc < N; ++cc) acc += ops[O.Lint + (r - 1) * N + cc] * sV[mv * NP + cv_point<N>(d, q, cc)];
+    Vf[mv] = acc;
+  }
+  Prim<double> st = ns_prim(c, Uf);
+  double Fc[5], Fv[5];
+  ns_conv_dir(c, Uf, st, sv, Fc);
+  ns_visc_dir(c, st, Vf, sv, Fv);
+  for (int v = 0; v < 5; ++v) sG[(d * 5 + v) * NI + w] = Fc[v] - Fv[v];
 }
 
 template <int N>
@@ -345,8 +468,13 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
   }
   __syncthreads();
   const NsConst<double> c(a);
-  // the element's half of the common flux at every face point
-  for (int t = tid; t < 6 * NF; t += nth) {
+  // one list of work items: the element's half of the common flux at every
+  // face point, then G_d at the interior flux points of family d
+  for (int t = tid; t < 6 * NF + 3 * NI; t += nth) {
+    if (t >= 6 * NF) {
+      cvn_interior_item<N>(c, ops, sS, sUF, sV, sG, t - 6 * NF);
+      continue;
+    }
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
     const double *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
     const double sv[3] = {srow[0], srow[1], srow[2]};
@@ -385,24 +513,6 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
     Prim<double> st = ns_prim(c, Uh);
     ns_visc_dir(c, st, Vf, sv, Fv);
     for (int v = 0; v < 5; ++v) X[(e * 6 + f) * 5 * NF + v * NF + q] = 0.5 * (nrm * Fr[v]) - 0.5 * Fv[v];
-  }
-  // G_d at the interior flux points of family d
-  for (int t = tid; t < 3 * NI; t += nth) {
-    const int d = t / NI, w = t % NI, q = w / (N - 1), r = 1 + w % (N - 1);
-    const double *srow = sS + ((d * NF + q) * (N + 1) + r) * 3;
-    const double sv[3] = {srow[0], srow[1], srow[2]};
-    double Uf[5], Vf[15];
-    for (int v = 0; v < 5; ++v) Uf[v] = sUF[(d * 5 + v) * NL + q * (N + 1) + r];
-    for (int mv = 0; mv < 15; ++mv) {
-      double acc = 0.0;
-      for (int cc = 0; cc < N; ++cc) acc += ops[O.Lint + (r - 1) * N + cc] * sV[mv * NP + cv_point<N>(d, q, cc)];
-      Vf[mv] = acc;
-    }
-    Prim<double> st = ns_prim(c, Uf);
-    double Fc[5], Fv[5];
-    ns_conv_dir(c, Uf, st, sv, Fc);
-    ns_visc_dir(c, st, Vf, sv, Fv);
-    for (int v = 0; v < 5; ++v) sG[(d * 5 + v) * NI + w] = Fc[v] - Fv[v];
   }
   __syncthreads();
   // their part of the divergence

@@ -70,37 +70,53 @@ __global__ void __launch_bounds__(256) k_dense_fwd(const uint16_t *__restrict__ 
 // C [M][N] = sum_k A(m, k) B(k, n) with strided operands on the FP32 matrix
 // cores (v_mfma_f32_16x16x4f32: lane l supplies A(l%16, k0 + l/16) and
 // B(k0 + l/16, l%16) and receives C[4(l/16)+j][l%16]), FP32 products and
-// sums.  One 16x16 tile of C per block of kGemmWaves wavefronts: wave w sums
-// the w-th contiguous quarter of the k range and the partial tiles are added
-// through LDS in wave order (a fixed order).  With GELU_BWD the tile is
+// sums.  One 16x16 tile of C per block of KW wavefronts: wave w sums the
+// w-th contiguous part of the k range (KW parts) and the partial tiles are
+// added through LDS in wave order (a fixed order).  With GELU_BWD the tile is
 // multiplied by gelu'(Z[m][n]) on the way out (the activation's backward).
+// With Bsum non-null, the blocks of the first column of tiles also write
+// Bsum[m] = sum_k A(m, k) (a layer's bias gradient when A is the output
+// gradient transposed), summed per lane, then over the four lane groups and
+// the waves in a fixed order.
 template <typename TA>
 __device__ __forceinline__ float ld_as_f32(const TA *p) {
   if constexpr (sizeof(TA) == 2) return from_bf16(*reinterpret_cast<const uint16_t *>(p));
   else return *p;
 }
 
-constexpr int kGemmWaves = 4;
-
-template <typename TA, typename TB, bool GELU_BWD>
-__global__ void __launch_bounds__(64 * kGemmWaves) k_gemm_mfma(int M, int N, int K, const TA *__restrict__ A,
+template <int KW, typename TA, typename TB, bool GELU_BWD>
+__global__ void __launch_bounds__(64 * KW) k_gemm_mfma(int M, int N, int K, const TA *__restrict__ A,
                                                                long long sam, long long sak,
                                                                const TB *__restrict__ B, long long sbk,
                                                                long long sbn, const float *__restrict__ Z,
-                                                               float *__restrict__ C) {
-  __shared__ float red[kGemmWaves - 1][4][64];
+                                                               float *__restrict__ C, float *__restrict__ Bsum) {
+  __shared__ float red[KW - 1][4][64];
+  __shared__ float bred[KW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
   const long long m = (long long)blockIdx.y * 16 + r, n = (long long)blockIdx.x * 16 + r;
-  const int kc = ((K + 4 * kGemmWaves - 1) / (4 * kGemmWaves)) * 4;
+  const int kc = ((K + 4 * KW - 1) / (4 * KW)) * 4;
   const int kb = w * kc, ke = min(K, kb + kc);
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  float asum = 0.f;
 #pragma unroll 4
   for (int k0 = kb; k0 < ke; k0 += 4) {
     const long long k = k0 + kq;
     const float a = (m < M && k < ke) ? ld_as_f32(A + m * sam + k * sak) : 0.f;
     const float b = (n < N && k < ke) ? ld_as_f32(B + k * sbk + n * sbn) : 0.f;
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    asum += a;
+  }
+  if (Bsum && blockIdx.x == 0) {
+    // uniform over the block
+    bred[w][lane] = asum;
+    __syncthreads();
+    if (w == 0 && kq == 0 && m < M) {
+      float t = 0.f;
+      for (int ww = 0; ww < KW; ++ww)
+        for (int g = 0; g < 4; ++g) t += bred[ww][16 * g + r];
+      Bsum[m] = t;
+    }
   }
   if (w > 0)
 #pragma unroll
@@ -110,7 +126,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_gemm_mfma(int M, int N, int
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     float v = acc[j];
-    for (int ww = 0; ww < kGemmWaves - 1; ++ww) v += red[ww][j][lane];
+    for (int ww = 0; ww < KW - 1; ++ww) v += red[ww][j][lane];
     const long long mo = (long long)blockIdx.y * 16 + 4 * kq + j;
     if (mo < M && n < N) {
       if constexpr (GELU_BWD) v *= gelu_prime_f(Z[mo * N + n]);
@@ -119,43 +135,43 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_gemm_mfma(int M, int N, int
   }
 }
 
-// out[n] = sum_b x[b][n], one thread per column, fixed order
-__global__ void k_colsum(const float *__restrict__ x, int B, int N, float *__restrict__ out) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) s += x[(long long)b * N + n];
-  out[n] = s;
+// dY = 2 w_r (Y - T) / n, one block of 256 lanes per 8 rows (elementwise)
+__global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T,
+                                                  const float *__restrict__ w, long long rows, int cols, float scale,
+                                                  float *__restrict__ dY) {
+  const long long r = (long long)blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (r >= rows) return;
+  const float wr = w ? w[r] : 1.0f;
+  for (int c = threadIdx.x & 31; c < cols; c += 32) {
+    const long long i = r * cols + c;
+    dY[i] = scale * wr * (Y[i] - T[i]);
+  }
 }
 
-// dY = 2 (Y - T) / n and per-block partial sums of (Y - T)^2
-__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ Y, const float *__restrict__ T,
-                                             const float *__restrict__ w, long long n, int cols,
-                                             float *__restrict__ dY, double *__restrict__ part) {
-  __shared__ double red[256];
+// loss = sum_r w_r sum_c (Y - T)^2 / n in FP64, one block, a fixed order:
+// lane l takes the rows l, l + 1024, ... whole, then the 1024 partial sums
+// are added pairwise
+__global__ void __launch_bounds__(1024) k_mse_loss(const float *__restrict__ Y, const float *__restrict__ T,
+                                                   const float *__restrict__ w, long long rows, int cols,
+                                                   double inv_n, double *__restrict__ loss) {
+  __shared__ double red[1024];
   double acc = 0.0;
-  const float scale = 2.0f / (float)n;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float d = Y[i] - T[i];
-    float wr = w ? w[i / cols] : 1.0f;
-    dY[i] = scale * wr * d;
-    acc += (double)wr * ((double)d * (double)d);
+  for (long long r = threadIdx.x; r < rows; r += blockDim.x) {
+    const double wr = w ? (double)w[r] : 1.0;
+    double rs = 0.0;
+    for (int c = 0; c < cols; ++c) {
+      const double d = (double)(Y[r * cols + c] - T[r * cols + c]);
+      rs += d * d;
+    }
+    acc += wr * rs;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-__global__ void k_sum_parts(const double *__restrict__ part, int nparts, double inv_n, double *__restrict__ out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[i];
-    *out = s * inv_n;
-  }
+  if (threadIdx.x == 0) *loss = red[0] * inv_n;
 }
 
 // Adam step with bias corrections c1 = 1/(1-b1^t), c2 = 1/(1-b2^t); Wb = bf16(P)

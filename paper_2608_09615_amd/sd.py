@@ -351,13 +351,14 @@ class Mlp:
 
 def mse(Y, T, dY, loss, w=None):
     """Row-weighted MSE of Y [rows, cols] against T: dY = 2 w (Y - T) / n and
-    the loss into a one-element FP64 device tensor; ``w`` [rows] FP32 or None."""
+    the loss into a one-element FP64 device tensor (``loss`` None: dY only);
+    ``w`` [rows] FP32 or None."""
     if Y.dim() != 2:
         raise ValueError("Y must be [rows, cols]")
     if w is not None and w.numel() != Y.shape[0]:
         raise ValueError("w must hold one weight per row")
     _check(load_library().sd_mse(_ptr(Y), _ptr(T), None if w is None else _ptr(w), Y.shape[0], Y.shape[1],
-                                 _ptr(dY), _ptr(loss), _stream()))
+                                 _ptr(dY), None if loss is None else _ptr(loss), _stream()))
 
 
 def filter_state(fine, nel_fine, ratio, p, nv):

@@ -77,6 +77,18 @@ def test_mse_and_adam(torch_cuda):
     lo, go = M.mse(y.astype(np.float64), t.astype(np.float64), w.astype(np.float64))
     assert abs(loss.item() - lo) < 1e-6 * lo
     assert np.abs(dY.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+    # without the loss: the same dY; more rows than the loss kernel's lanes
+    dY.zero_()
+    mse(torch.from_numpy(y).to("cuda"), torch.from_numpy(t).to("cuda"), dY, None, w=torch.from_numpy(w).to("cuda"))
+    assert np.abs(dY.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+    y2 = rng.normal(size=(2500, 320)).astype(np.float32)
+    t2 = rng.normal(size=(2500, 320)).astype(np.float32)
+    w2 = rng.uniform(0, 3, 2500).astype(np.float32)
+    dY2 = torch.empty((2500, 320), dtype=torch.float32, device="cuda")
+    mse(torch.from_numpy(y2).to("cuda"), torch.from_numpy(t2).to("cuda"), dY2, loss, w=torch.from_numpy(w2).to("cuda"))
+    lo, go = M.mse(y2.astype(np.float64), t2.astype(np.float64), w2.astype(np.float64))
+    assert abs(loss.item() - lo) < 1e-6 * lo
+    assert np.abs(dY2.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
     net, p = make_net(torch, 64, 32, 48, seed=6)
     P0 = M.flatten(p)
     m = np.zeros_like(P0)
@@ -243,24 +255,34 @@ def test_training_reduces_loss(torch_cuda):
     assert losses[-1] < 0.1 * losses[0]
 
 
-def test_trained_closure_gains_on_held_out_seed(torch_cuda):
+def test_trained_closure_gains_on_held_out_seeds(torch_cuda):
     """End to end on a small case (16^3 fine -> 8^3 coarse elements, p = 3,
-    Re = 5000): pairs from the fine runs of three seeds with symmetry images,
-    training with the library's kernels, and on a held-out seed the trained
-    network removes a clear part of the coarse residual error (a priori);
-    the corrected coarse runs stay finite."""
+    Re = 5000, to t = 8): the fine runs of three seeds give the training
+    pairs (the coarse scheme's trajectory defect over each interval of 0.5,
+    with 8 cube-symmetry images), the network is trained with the library's
+    kernels, and on two held-out seeds the coarse run with the closure tracks
+    the filtered fine run better than the plain coarse run, in kinetic
+    energy and in enstrophy (measured: seed 3, KE error 0.092 -> 0.069 and
+    enstrophy error 0.239 -> 0.078; seed 7, 0.058 -> 0.037 and 0.290 ->
+    0.140), with no interval handed back to the plain scheme."""
     torch = torch_cuda
     from paper_2608_09615_amd import closure as C
-    print("[closure e2e] 16^3 -> 8^3, seeds 0-2, held-out 3", flush=True)
+    log = lambda s: print(s, flush=True)
+    print("[closure e2e] 16^3 -> 8^3, seeds 0-2, held-out 3 and 7", flush=True)
     prob = C.Problem(nel_f=16, ratio=2, p=3, Re=5000.0)
-    net, norm, losses, ns = C.train(torch, prob, [0, 1, 2], t_end=6.0, dt_snap=0.5, n_sym=16, iters=3000,
-                                    log=lambda s: print(s, flush=True))
-    assert ns == 3 * 12 * 512 * 16
-    assert losses[-1][1] < 0.7 * losses[0][1]
-    out = C.evaluate(torch, prob, 3, 6.0, 0.5, net, norm, variants=[("closure", 4.0, 1e-3), ("unbounded", 0.0, 1e-3)],
-                     log=lambda s: print(s, flush=True))
-    print(out["a_priori"]["ratio"], flush=True)
-    assert out["a_priori"]["ratio"] < 0.9
-    for name in ("plain", "closure", "unbounded"):
-        assert np.all(np.isfinite(out[name]["ke"])) and np.all(np.isfinite(out[name]["enstrophy"]))
-    assert out["plain"]["fallback_intervals"] == []
+    net, norm, losses, ns = C.train(torch, prob, [0, 1, 2], t_end=8.0, dt_snap=0.5, n_sym=8, iters=2000,
+                                    log=log, target="interval")
+    assert ns == 3 * 16 * 512 * 8
+    assert losses[-1][1] < losses[0][1]
+    for seed in (3, 7):
+        out = C.evaluate(torch, prob, seed, 8.0, 0.5, net, norm, variants=[("closure", 1.0, 1e-3)], log=log,
+                         target="interval")
+        plain, corr = out["plain"], out["closure"]
+        print(f"seed {seed}: a priori {out['a_priori']['ratio']:.3f}; KE error {plain['ke_err']:.4f} -> "
+              f"{corr['ke_err']:.4f}, enstrophy error {plain['ens_err']:.4f} -> {corr['ens_err']:.4f}", flush=True)
+        assert out["a_priori"]["ratio"] < 0.95
+        assert corr["ke_err"] < 0.85 * plain["ke_err"]
+        assert corr["ens_err"] < 0.85 * plain["ens_err"]
+        assert corr["fallback_intervals"] == [] and plain["fallback_intervals"] == []
+        for name in ("plain", "closure"):
+            assert np.all(np.isfinite(out[name]["ke"])) and np.all(np.isfinite(out[name]["enstrophy"]))
