@@ -471,6 +471,29 @@ def training_bench(torch, args, p=3, hidden=128, batch=1024, steps=200):
             "tflops": tf, "frac_fp32_mfma": tf / PEAK_FP32_MFMA_TFLOPS}
 
 
+def closure_record():
+    """The trained closure's errors and speedup on the held-out seed(s) of the
+    64^3 -> 16^3 case (profiles/closure_64to16_p3_seed*.json, written by
+    paper_2608_09615_amd.closure; the command is in each record)."""
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "closure_64to16_p3_seed*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        post = rec["a_posteriori"]
+        trained = rec["config"].get("trained_with") or rec["config"]
+        out.append({"record": os.path.relpath(path, ROOT), "test_seed": rec["config"]["test_seed"],
+                    "train_seeds": trained["train_seeds"],
+                    "target": rec["config"]["target"], "dt_snap": rec["config"]["dt_snap"],
+                    "a_priori_ratio": rec["a_priori"]["ratio"],
+                    "ke_err": {k: post[k]["ke_err"] for k in ("plain", "closure")},
+                    "ens_err": {k: post[k]["ens_err"] for k in ("plain", "closure")},
+                    "wall_s": {"fine": post["wall_fine_s"], "plain": post["plain"]["wall_s"],
+                               "closure": post["closure"]["wall_s"]},
+                    "speedup_vs_fine": rec.get("speedup_vs_fine")})
+    return out
+
+
 def closure_traffic(N, p, hidden):
     """HBM bytes per k_closure_fused launch from the committed counter
     record, or None for another workload or once a source it is keyed to
@@ -629,6 +652,7 @@ def main():
         rec["curvilinear_ns"] = curvilinear_bench(torch, args, physics="ns")
     if args.closure_nel > 0:
         rec["closure"] = closure_bench(torch, args)
+        rec["closure"]["a_posteriori_64to16"] = closure_record()
         rec["closure_training"] = training_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0, fp64_rhs(torch, args, U0))

@@ -428,6 +428,12 @@ def run(nel_f=64, ratio=4, p=3, Re=5000.0, train_seeds=range(7), test_seed=7, t_
             saved = json.load(f)
         norm = tuple(saved["norm"])
         res["train"] = saved.get("train")
+        # the loaded network's own training configuration replaces the
+        # training fields of this run's
+        for k in ("train_seeds", "n_sym", "hidden", "iters", "batch", "lr", "weight_power"):
+            cfg.pop(k, None)
+        cfg["loaded"] = list(load)
+        cfg["trained_with"] = saved.get("config")
     else:
         net, norm, losses, ns = train(torch, prob, list(train_seeds), t_end, dt_snap, n_sym, hidden, iters, batch,
                                       lr, weight_power, log=log, target=target)

@@ -30,3 +30,18 @@ def test_traffic_record_applies_to_its_workload_only():
     for change in (dict(nel=64), dict(p=5), dict(scheme="br1"), dict(eta_ip=0.1), dict(integrator="ssprk54")):
         args = argparse.Namespace(**{**base, **change})
         assert bench.measured_traffic(args, "fp32") is None, change
+
+
+def test_closure_record_shows_the_gain():
+    """The committed 64^3 -> 16^3 closure record(s): on each held-out seed
+    the corrected coarse run's KE and enstrophy errors are below the plain
+    coarse run's, and the corrected run is faster than the fine run."""
+    sys.path.insert(0, ROOT)
+    import bench
+    recs = bench.closure_record()
+    assert recs, "no closure record under profiles/"
+    for r in recs:
+        assert r["test_seed"] >= 8 and r["target"] == "interval"
+        assert r["ke_err"]["closure"] < r["ke_err"]["plain"]
+        assert r["ens_err"]["closure"] < r["ens_err"]["plain"]
+        assert r["wall_s"]["closure"] < r["wall_s"]["fine"] / 10

@@ -1,6 +1,7 @@
 """GPU closure kernels against the FP64 reference (oracle/mlp.py): BF16-MFMA
-forward, FP32 backward, MSE, Adam, the fine-to-coarse filter, and the
-closure inside the solver (correction and per-element fallback)."""
+forward, FP32-MFMA backward, MSE, Adam, the fine-to-coarse filter, the
+closure inside the solver (correction and per-element fallback), and the
+trained closure's gain over the plain coarse scheme."""
 import numpy as np
 import pytest
 
@@ -45,8 +46,12 @@ def test_mlp_forward_matches_reference(torch_cuda, shape, B):
     assert err.max() < 2e-2 * scale
 
 
-@pytest.mark.parametrize("shape,B", [((64, 32, 48), 100), ((320, 128, 320), 512)])
+@pytest.mark.parametrize("shape,B", [((64, 32, 48), 100), ((64, 32, 48), 1), ((64, 32, 48), 37),
+                                     ((320, 128, 320), 512), ((320, 128, 320), 1027)])
 def test_mlp_backward_matches_reference(torch_cuda, shape, B):
+    """Weight and bias gradients (the bias sums fused into the weight-gradient
+    products) for batches that fill the k split of the matrix-core products
+    unevenly: 1, 37, 100 and 1027 samples."""
     print(f"[mlp bwd] {shape} B={B}", flush=True)
     net, p = make_net(torch_cuda, *shape, seed=3)
     rng = np.random.Generator(np.random.PCG64(4))
