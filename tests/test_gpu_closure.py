@@ -40,6 +40,8 @@ def test_mlp_forward_matches_reference(torch_cuda, shape, B):
     yo, _ = M.forward(p, x.astype(np.float64), bf16=True)
     err = np.abs(y - yo)
     scale = np.abs(yo).max()
+    print(f"forward {shape} B={B}: max error {err.max() / scale:.2e} of max|y|, "
+          f"{np.mean(err < 1e-5 * scale):.5f} within 1e-5, {np.mean(err < 1e-4 * scale):.5f} within 1e-4", flush=True)
     # products differ by FP32 accumulation only; a BF16 rounding of an
     # activation taken on the other side of a tie may move a few outputs
     assert np.mean(err < 1e-4 * scale) > 0.999
@@ -161,6 +163,9 @@ def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
         # same bar as the forward test: BF16 roundings of activations may fall
         # on the other side of a tie for a few values
         d = np.abs(R - ref)
+        ys = out_scale * np.abs(Yo).max()
+        print(f"closure in solver n_h={n_h} out_scale={out_scale:g} max_ratio={max_ratio:g}: max error "
+              f"{(d.max() - 1e-11 * np.abs(Ro).max()) / ys:.2e} of max|C|", flush=True)
         assert d.max() < 2e-2 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()
         assert np.mean(d < 1e-4 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()) > 0.999
         sd.close()

@@ -15,17 +15,18 @@ pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-12
 # FP32 (reference state removed for Navier-Stokes): contractions in single
 # precision over n <= 7 terms on O(1) data, fluxes in single precision; the
-# bound is a few hundred FP32 ulps of the largest term, normwise.
+# bound is a few hundred FP32 ulps of the largest term, normwise (measured
+# at most 7.0e-5 for Navier-Stokes, at 32^3 with BR1).
 FP32_TOL_SCALAR = 2e-5
-FP32_TOL_NS = 2e-4
+FP32_TOL_NS = 1e-4
 # BF16x3 (gradient and divergence contractions as hi*hi + hi*lo + lo*hi BF16
 # products, FP32 accumulation; everything else as FP32): each split operand
 # carries ~2^-18 relative error, so one directional divergence is good to
 # ~1e-5 of its size.  The density and energy residuals are sums of three
 # directional divergences that cancel to ~1/300 of their size at Ma = 0.1
 # (div(rho u) and div((rho E + p) u) ~ Ma^2), which leaves ~3e-3 normwise in
-# those two variables (momentum ~3e-5); the gate is 1e-2.
-BF16X3_TOL_NS = 1e-2
+# those two variables (momentum ~3e-5); measured at most 4.8e-3 (p = 5).
+BF16X3_TOL_NS = 6e-3
 
 
 @pytest.fixture(scope="module")
@@ -154,6 +155,7 @@ def test_ns_entropy_fix_branch_parity(torch_cuda, oracle_lib, scheme, p):
     print(f"entropy-fix faces, NS p={p} {scheme}: FP64 {err:.2e} (fix changes the RHS by {relerr(Roff, Ro):.1e})")
     assert err < FP64_TOL
     R32, _ = gpu_rhs(torch_cuda, U, nel, p, scheme, "ns", "fp32", lo, hi, Re=400.0)
+    print(f"entropy-fix faces, NS p={p} {scheme}: FP32 {relerr(R32, Ro):.2e}")
     assert relerr(R32, Ro) < FP32_TOL_NS
 
 
