@@ -67,6 +67,8 @@ def parse():
                     help="elements per direction of the curvilinear workloads (0: skip them)")
     ap.add_argument("--curv-p", type=int, default=3, help="degree of the curvilinear workloads")
     ap.add_argument("--curv-scheme", default="compact", choices=["compact", "br1"])
+    ap.add_argument("--curv-precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the --only curvilinear workloads")
     ap.add_argument("--closure-nel", type=int, default=16,
                     help="elements per direction of the learned-closure timing (0: skip it)")
     ap.add_argument("--only", choices=["bloch", "curvilinear", "curvilinear_ns", "closure", "training"],
@@ -318,7 +320,7 @@ def bloch_bench(torch, args, p=3, scheme="compact", reps=5):
                          "kernels": "k_bloch_lane_cm (combined mode)"}}
 
 
-def curvilinear_bench(torch, args, reps=20, physics="diffusion"):
+def curvilinear_bench(torch, args, reps=20, physics="diffusion", precision="fp64"):
     """Right-hand side on curvilinear hexahedra (degree-2 elements of a
     periodic box moved by a smooth wave of amplitude 0.3), FP64, one RHS per
     step: linear diffusion of a smooth field, or the Navier-Stokes equations
@@ -337,13 +339,14 @@ def curvilinear_bench(torch, args, reps=20, physics="diffusion"):
     if physics == "ns":
         nv = 5
         lo, hi = W.tgv_domain()
-        sd = SD(nel, p, scheme=scheme, physics="ns", lo=lo, hi=hi, Re=1600.0, Ma=0.1, Pr=0.71)
+        sd = SD(nel, p, scheme=scheme, physics="ns", precision=precision, lo=lo, hi=hi, Re=1600.0, Ma=0.1,
+                Pr=0.71)
         u = torch.from_numpy(W.perturbed_tgv_state(nel, p, seed=0)).to("cuda")
         what = "compressible Navier-Stokes (Taylor-Green state, Re=1600, Ma=0.1)"
         kernels = "k_cvn_traces + k_cvn_grad + k_cvn_face"
     else:
         nv = 1
-        sd = SD(nel, p, scheme=scheme, physics="diffusion", lo=[0.0] * 3, hi=[1.0] * 3)
+        sd = SD(nel, p, scheme=scheme, physics="diffusion", precision=precision, lo=[0.0] * 3, hi=[1.0] * 3)
         x = W.map_points(Xg, p)
         u = torch.from_numpy(np.ascontiguousarray((np.sin(x[..., 0]) * np.sin(x[..., 1]) * np.sin(x[..., 2]))[:, None]))
         u = u.to("cuda")
@@ -364,13 +367,16 @@ def curvilinear_bench(torch, args, reps=20, physics="diffusion"):
     ms = e0.elapsed_time(e1) / reps
     sd.close()
     dof = N ** 3 * n ** 3
-    bytes_el = 16.0 * nv * n ** 3 + 8.0 * (9 * (n + 1) * n * n + n ** 3)
+    # metric terms in the compute type (8 B in FP64, 4 B in FP32)
+    mb = 8.0 if precision == "fp64" else 4.0
+    bytes_el = 16.0 * nv * n ** 3 + mb * (9 * (n + 1) * n * n + n ** 3)
     gbs = bytes_el * N ** 3 / (ms * 1e-3) / 1e9
     return {"config": f"{what}, {N}^3 degree-2 hexahedra (periodic box, wave displacement 0.3), "
-                      f"p={p} {scheme}, FP64",
+                      f"p={p} {scheme}, {precision.upper()}",
             "gdofs_per_rhs": dof / ms / 1e6, "ms_per_rhs": ms, "variables": nv,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": curv_traffic(N, p, scheme, physics),
+                         "frac": gbs / PEAK_HBM_GBS,
+                         "traffic": curv_traffic(N, p, scheme, physics) if precision == "fp64" else None,
                          "traffic_unit": "B per RHS", "kernels": kernels}}
 
 
@@ -556,10 +562,11 @@ def main():
         print(json.dumps({"bloch": bloch_bench(torch, args)}), flush=True)
         return
     if args.only == "curvilinear":
-        print(json.dumps({"curvilinear": curvilinear_bench(torch, args)}), flush=True)
+        print(json.dumps({"curvilinear": curvilinear_bench(torch, args, precision=args.curv_precision)}), flush=True)
         return
     if args.only == "curvilinear_ns":
-        print(json.dumps({"curvilinear_ns": curvilinear_bench(torch, args, physics="ns")}), flush=True)
+        print(json.dumps({"curvilinear_ns": curvilinear_bench(torch, args, physics="ns",
+                                                              precision=args.curv_precision)}), flush=True)
         return
     if args.only == "closure":
         print(json.dumps({"closure": closure_bench(torch, args)}), flush=True)
@@ -650,6 +657,8 @@ def main():
     if args.curv_nel > 0:
         rec["curvilinear"] = curvilinear_bench(torch, args)
         rec["curvilinear_ns"] = curvilinear_bench(torch, args, physics="ns")
+        rec["curvilinear"]["fp32"] = curvilinear_bench(torch, args, precision="fp32")
+        rec["curvilinear_ns"]["fp32"] = curvilinear_bench(torch, args, physics="ns", precision="fp32")
     if args.closure_nel > 0:
         rec["closure"] = closure_bench(torch, args)
         rec["closure"]["a_posteriori_64to16"] = closure_record()

@@ -6,8 +6,9 @@
  * written as the first-order system with the auxiliary gradient v = grad u
  * and mapped to the reference hexahedron (Lodato & Tonicello, section 2,
  * eqs. ns and ns:mapped/adj:f), on structured periodic hexahedral meshes:
- * uniform Cartesian ones, or (3-D diffusion and Navier-Stokes, FP64)
- * curvilinear elements given by their node coordinates (sd_set_geometry).
+ * uniform Cartesian ones, or (3-D diffusion and Navier-Stokes, FP64 or
+ * FP32) curvilinear elements given by their node coordinates
+ * (sd_set_geometry).
  * The
  * auxiliary gradient is reconstructed either with the standard BR1-type
  * centred treatment (section 2.1: common solution eq. c:flux, gradient
@@ -169,7 +170,10 @@ int sd_diagnostics(sd_ctx *ctx, const double *u, sd_diag *out);
 int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
 
 /* Curvilinear hexahedra (section 2.3: q = J u, G = S.F, H = S^T u with
- * S = adj(dx/dxi)) for a 3-D diffusion or Navier-Stokes context in FP64.
+ * S = adj(dx/dxi)) for a 3-D diffusion or Navier-Stokes context in FP64 or
+ * FP32 (SD_FP32: the metric terms are stored and used in FP32, and the
+ * Navier-Stokes reference state is removed before the rounding as on
+ * Cartesian meshes; the state and the RHS stay FP64 in memory).
  * Navier-Stokes (p <= 5): G_d = S_d . (F_c - F_v) at the flux points of
  * family d; at a face the Roe flux along n = S_d / |S_d| times |S_d| (the
  * Harten fix as on Cartesian meshes) minus S_d . F_v of the averaged
@@ -188,7 +192,8 @@ int sd_stable_dt(sd_ctx *ctx, const double *u, double cfl, double *dt);
  * are preserved exactly when 2q <= p + 1.  Returns SD_EINVAL for a null
  * argument, q outside {1, 2} or an element whose det J is not positive at
  * a solution point (or, with the interior penalty on, at a face point);
- * SD_EUNSUPPORTED for other physics, dimensions or precisions, for
+ * SD_EUNSUPPORTED for other physics, dimensions or precisions (BF16x3,
+ * FP32 matrix cores), for
  * Navier-Stokes at p > 5 or with the interior penalty, and for a context
  * whose closure is set; SD_ENOMEM /
  * SD_EHIP on device failures.  With eta_ip > 0 the penalty uses, at each

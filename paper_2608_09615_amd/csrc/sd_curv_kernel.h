@@ -1,5 +1,7 @@
 // SD diffusion right-hand side on curvilinear hexahedra (section 2.3 with a
-// general adjoint S), scalar u_t = nu lap u, FP64.
+// general adjoint S), scalar u_t = nu lap u, in FP64 or FP32 (the compute
+// type R of the metric terms, the work buffers and the arithmetic; the state
+// is read and the RHS written in FP64).
 //
 // Geometry per element: S row d (S_d0, S_d1, S_d2) at the flux points of
 // family d and 1/det J at the solution points, stored line-major: for
@@ -62,71 +64,86 @@ __device__ __forceinline__ void cv_line_of(int pt, int d, int &q, int &c) {
   }
 }
 
-// trace of one variable (n^3 values at u) at point q of face f = 2 d + s;
-// k_cv_traces and k_cv_grad evaluate an element's traces with this same
-// sequence of operations, so both see the same values
-template <int N>
-__device__ __forceinline__ double cv_trace(const double *__restrict__ ops, const double *u, int d, int s, int q) {
+// trace at point q of face f = 2 d + s from the n values v[c] of its line
+// (already in the compute type): k_cv_traces and k_cv_grad evaluate an
+// element's traces with this same sequence of operations on the same
+// rounded values, so both see the same traces
+template <int N, typename R>
+__device__ __forceinline__ R cv_dot_end(const R *__restrict__ ops, const R *v, int s) {
   constexpr OpsLayout O = ops_layout(N);
-  double acc = 0.0;
+  R acc = R(0);
 #pragma unroll
-  for (int c = 0; c < N; ++c) acc += ops[O.Lend + s * N + c] * u[cv_point<N>(d, q, c)];
+  for (int c = 0; c < N; ++c) acc += ops[O.Lend + s * N + c] * v[c];
   return acc;
 }
 
-template <int N>
-__global__ void __launch_bounds__(cv_threads<N>()) k_cv_traces(const double *__restrict__ U, double *__restrict__ T,
-                                                          const double *__restrict__ ops, long long ne) {
+// the state in the compute type, minus the subtracted constant (the
+// reference state of the Navier-Stokes variables; 0 otherwise)
+template <typename R>
+__device__ __forceinline__ R cv_in(double u, double shift) {
+  return (R)(u - shift);
+}
+
+template <int N, typename R>
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_traces(const double *__restrict__ U, R *__restrict__ T,
+                                                          const R *__restrict__ ops, long long ne) {
   constexpr int NP = N * N * N, NF = N * N;
   const long long e = blockIdx.x;
   if (e >= ne) return;
   const double *u = U + e * NP;
   for (int t = threadIdx.x; t < 6 * NF; t += blockDim.x) {
-    const int f = t / NF, q = t % NF;
-    T[e * 6 * NF + t] = cv_trace<N>(ops, u, f >> 1, f & 1, q);
+    const int f = t / NF, q = t % NF, d = f >> 1;
+    R v[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = cv_in<R>(u[cv_point<N>(d, q, c)], 0.0);
+    T[e * 6 * NF + t] = cv_dot_end<N>(ops, v, f & 1);
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__restrict__ U, const double *__restrict__ T,
-                                                        const double *__restrict__ Sf, const double *__restrict__ Jinv,
-                                                        const double *__restrict__ ops, KArgs a, int compact,
-                                                        double *__restrict__ W, double *__restrict__ Part) {
+template <int N, typename R>
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__restrict__ U, const R *__restrict__ T,
+                                                        const R *__restrict__ Sf, const R *__restrict__ Jinv,
+                                                        const R *__restrict__ ops, KArgs a, int compact,
+                                                        R *__restrict__ W, R *__restrict__ Part) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF, NI = (N - 1) * NF;
-  __shared__ double sS[9 * NL], su[NP], sJ[NP], sT[6 * NF], sUh[6 * NF], sUF[3 * NL], sV[3 * NP];
+  __shared__ R sS[9 * NL], su[NP], sJ[NP], sT[6 * NF], sUh[6 * NF], sUF[3 * NL], sV[3 * NP];
   // the interior fluxes [d][q][r - 1] take the place of the flux-point
   // solution once the gradient is formed
-  double *sG = sUF;
+  R *sG = sUF;
   static_assert(3 * NI <= 3 * NL, "interior fluxes fit the flux-point solution's place");
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x;
+  const R nu = (R)a.nu;
   for (int t = tid; t < 9 * NL; t += blockDim.x) sS[t] = Sf[e * 9 * NL + t];
   for (int t = tid; t < NP; t += blockDim.x) {
-    su[t] = U[e * NP + t];
+    su[t] = cv_in<R>(U[e * NP + t], 0.0);
     sJ[t] = Jinv[e * NP + t];
   }
   __syncthreads();
   // own traces and the common solution at the faces
   for (int t = tid; t < 6 * NF; t += blockDim.x) {
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
-    const double own = cv_trace<N>(ops, su, d, s, q);
-    const double oth = T[nbr(a, e, d, s) * 6 * NF + (2 * d + 1 - s) * NF + q];
+    R v[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = su[cv_point<N>(d, q, c)];
+    const R own = cv_dot_end<N>(ops, v, s);
+    const R oth = T[nbr(a, e, d, s) * 6 * NF + (2 * d + 1 - s) * NF + q];
     sT[t] = own;
-    sUh[t] = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+    sUh[t] = s == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
   }
   __syncthreads();
   // continuous solution at the flux points of every family
   for (int t = tid; t < 3 * NL; t += blockDim.x) {
     const int d = t / NL, w = t % NL, q = w / (N + 1), r = w % (N + 1);
-    double val;
+    R val;
     if (r == 0) {
       val = sUh[(2 * d) * NF + q];
     } else if (r == N) {
       val = sUh[(2 * d + 1) * NF + q];
     } else {
-      val = 0.0;
+      val = R(0);
       for (int c = 0; c < N; ++c) val += ops[O.Lint + (r - 1) * N + c] * su[cv_point<N>(d, q, c)];
     }
     sUF[t] = val;
@@ -135,11 +152,11 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
   // auxiliary variable at the solution points
   for (int t = tid; t < 3 * NP; t += blockDim.x) {
     const int m = t / NP, pt = t % NP;
-    double acc = 0.0;
+    R acc = R(0);
     for (int d = 0; d < 3; ++d) {
       int q, c;
       cv_line_of<N>(pt, d, q, c);
-      double dd = 0.0;
+      R dd = R(0);
       for (int r = 0; r <= N; ++r)
         dd += ops[O.M + c * (N + 1) + r] * (sUF[d * NL + q * (N + 1) + r] * sS[((d * NF + q) * (N + 1) + r) * 3 + m]);
       acc += dd;
@@ -150,22 +167,22 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
   // values at the faces, projected on the face's S row
   for (int t = tid; t < 6 * NF; t += blockDim.x) {
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
-    const double *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
+    const R *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
     int rend = 0;
-    double jump = 0.0;
+    R jump = R(0);
     if (compact) {
       // the family-d solution of face s keeps the own trace at the other face
       const int so = 1 - s;
       rend = so == 0 ? 0 : N;
       jump = sT[(2 * d + so) * NF + q] - sUh[(2 * d + so) * NF + q];
     }
-    double w = 0.0;
+    R w = R(0);
     for (int m = 0; m < 3; ++m) {
-      const double corr = compact ? jump * sS[((d * NF + q) * (N + 1) + rend) * 3 + m] : 0.0;
-      double acc = 0.0;
+      const R corr = compact ? jump * sS[((d * NF + q) * (N + 1) + rend) * 3 + m] : R(0);
+      R acc = R(0);
       for (int c = 0; c < N; ++c) {
         const int pt = cv_point<N>(d, q, c);
-        double v = sV[m * NP + pt];
+        R v = sV[m * NP + pt];
         if (compact) v += sJ[pt] * (ops[O.M + c * (N + 1) + rend] * corr);
         acc += ops[O.Lend + s * N + c] * v;
       }
@@ -176,22 +193,22 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
   // G_d = -nu S_d . v at the interior flux points of family d
   for (int t = tid; t < 3 * NI; t += blockDim.x) {
     const int d = t / NI, w = t % NI, q = w / (N - 1), r = 1 + w % (N - 1);
-    double g = 0.0;
+    R g = R(0);
     for (int m = 0; m < 3; ++m) {
-      double v = 0.0;
+      R v = R(0);
       for (int c = 0; c < N; ++c) v += ops[O.Lint + (r - 1) * N + c] * sV[m * NP + cv_point<N>(d, q, c)];
       g += sS[((d * NF + q) * (N + 1) + r) * 3 + m] * v;
     }
-    sG[t] = -a.nu * g;
+    sG[t] = -nu * g;
   }
   __syncthreads();
   // their part of the divergence
   for (int pt = tid; pt < NP; pt += blockDim.x) {
-    double acc = 0.0;
+    R acc = R(0);
     for (int d = 0; d < 3; ++d) {
       int q, c;
       cv_line_of<N>(pt, d, q, c);
-      double dd = 0.0;
+      R dd = R(0);
       for (int r = 1; r < N; ++r) dd += ops[O.M + c * (N + 1) + r] * sG[d * NI + q * (N - 1) + r - 1];
       acc += dd;
     }
@@ -199,41 +216,40 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(cv_threads<N>()) k_cv_face(const double *__restrict__ W,
-                                                        const double *__restrict__ Part,
-                                                        const double *__restrict__ Jinv,
-                                                        const double *__restrict__ ops, KArgs a,
-                                                        const double *__restrict__ T,
-                                                        const double *__restrict__ Pen, double *__restrict__ dudt) {
+template <int N, typename R>
+__global__ void __launch_bounds__(cv_threads<N>()) k_cv_face(const R *__restrict__ W, const R *__restrict__ Part,
+                                                        const R *__restrict__ Jinv, const R *__restrict__ ops,
+                                                        KArgs a, const R *__restrict__ T, const R *__restrict__ Pen,
+                                                        double *__restrict__ dudt) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N;
-  __shared__ double sGf[6 * NF];
+  __shared__ R sGf[6 * NF];
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x;
+  const R nu = (R)a.nu;
   for (int t = tid; t < 6 * NF; t += blockDim.x) {
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
     const long long en = nbr(a, e, d, s);
-    const double own = W[e * 6 * NF + t];
-    const double oth = W[en * 6 * NF + (2 * d + 1 - s) * NF + q];
-    double g = s == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+    const R own = W[e * 6 * NF + t];
+    const R oth = W[en * 6 * NF + (2 * d + 1 - s) * NF + q];
+    R g = s == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
     if (Pen) {
       // interior penalty: P' (u_R - u_L), u_R on the +xi_d side
-      const double to = T[e * 6 * NF + t], tn = T[en * 6 * NF + (2 * d + 1 - s) * NF + q];
+      const R to = T[e * 6 * NF + t], tn = T[en * 6 * NF + (2 * d + 1 - s) * NF + q];
       g += Pen[e * 6 * NF + t] * (s == 0 ? to - tn : tn - to);
     }
-    sGf[t] = -a.nu * g;
+    sGf[t] = -nu * g;
   }
   __syncthreads();
   for (int pt = tid; pt < NP; pt += blockDim.x) {
-    double acc = Part[e * NP + pt];
+    R acc = Part[e * NP + pt];
     for (int d = 0; d < 3; ++d) {
       int q, c;
       cv_line_of<N>(pt, d, q, c);
       acc += ops[O.M + c * (N + 1)] * sGf[(2 * d) * NF + q] + ops[O.M + c * (N + 1) + N] * sGf[(2 * d + 1) * NF + q];
     }
-    dudt[e * NP + pt] = -Jinv[e * NP + pt] * acc;
+    dudt[e * NP + pt] = (double)(-Jinv[e * NP + pt] * acc);
   }
 }
 
@@ -241,8 +257,10 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_face(const double *__res
 
 // ---------------------------------------------------------------------------
 // Navier-Stokes on curvilinear hexahedra (section 2.3, eqs. ns:mapped and
-// adj:f; fluxes of section 4.4), FP64.  The same three steps for the five
-// conservative variables (traces T[e][f][v][q]):
+// adj:f; fluxes of section 4.4), FP64 or FP32 as above, the constant
+// reference state removed before the rounding to the compute type (as on
+// Cartesian meshes).  The same three steps for the five conservative
+// variables (traces T[e][f][v][q]):
 //   k_cvn_grad  the gradient of every variable at the solution points (kept
 //               in LDS), its one-sided (compact) or standard face values,
 //               the fluxes G_d = S_d . (F_c - F_v) at the interior flux
@@ -360,92 +378,100 @@ __device__ __forceinline__ void ns_roe_dir(const NsConst<R> &c, const R *UL, con
 
 constexpr int kCvnThreads = 256;
 
+// LDS of k_cvn_grad in elements of the compute type
 template <int N>
 struct CvnGradSmem {
   static constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF, NI = (N - 1) * NF;
   static constexpr int S = 0, U = S + 9 * NL, J = U + 5 * NP, T = J + NP, TN = T + 30 * NF, UF = TN + 30 * NF,
                        V = UF + 15 * NL, G = V + 15 * NP;
-  static constexpr int TOTAL = G + 15 * NI;   // doubles
+  static constexpr int TOTAL = G + 15 * NI;
 };
 
-template <int N>
-__global__ void __launch_bounds__(kCvnThreads) k_cvn_traces(const double *__restrict__ U, double *__restrict__ T,
-                                                            const double *__restrict__ ops, long long ne) {
+template <int N, typename R>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_traces(const double *__restrict__ U, R *__restrict__ T,
+                                                            const R *__restrict__ ops, KArgs a) {
   constexpr int NP = N * N * N, NF = N * N;
   const long long e = blockIdx.x;
-  if (e >= ne) return;
+  if (e >= a.ne) return;
   for (int t = threadIdx.x; t < 30 * NF; t += blockDim.x) {
-    const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF;
-    T[e * 30 * NF + t] = cv_trace<N>(ops, U + (e * 5 + v) * NP, f >> 1, f & 1, q);
+    const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF, d = f >> 1;
+    const double *u = U + (e * 5 + v) * NP;
+    R x[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] = cv_in<R>(u[cv_point<N>(d, q, c)], a.U0[v]);
+    T[e * 30 * NF + t] = cv_dot_end<N>(ops, x, f & 1);
   }
 }
 
 // common solution at point q of face f for variable v, from the own and the
 // neighbour's trace (the same expression on both sides of the face)
-__device__ __forceinline__ double cvn_hat(const double *sT, const double *sTn, int f, int idx) {
-  const double own = sT[idx], oth = sTn[idx];
-  return (f & 1) == 0 ? 0.5 * (oth + own) : 0.5 * (own + oth);
+template <typename R>
+__device__ __forceinline__ R cvn_hat(const R *sT, const R *sTn, int f, int idx) {
+  const R own = sT[idx], oth = sTn[idx];
+  return (f & 1) == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
 }
 
 // G_d = S_d . (F_c - F_v) at interior flux point w of family d (item t)
-template <int N>
-__device__ __forceinline__ void cvn_interior_item(const NsConst<double> &c, const double *__restrict__ ops,
-                                                  const double *sS, const double *sUF, const double *sV, double *sG,
-                                                  int t) {
+template <int N, typename R>
+__device__ __forceinline__ void cvn_interior_item(const NsConst<R> &c, const R *__restrict__ ops, const R *sS,
+                                                  const R *sUF, const R *sV, R *sG, int t) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF, NI = (N - 1) * NF;
   const int d = t / NI, w = t % NI, q = w / (N - 1), r = 1 + w % (N - 1);
-  const double *srow = sS + ((d * NF + q) * (N + 1) + r) * 3;
-  const double sv[3] = {srow[0], srow[1], srow[2]};
-  double Uf[5], Vf[15];
+  const R *srow = sS + ((d * NF + q) * (N + 1) + r) * 3;
+  const R sv[3] = {srow[0], srow[1], srow[2]};
+  R Uf[5], Vf[15];
   for (int v = 0; v < 5; ++v) Uf[v] = sUF[(d * 5 + v) * NL + q * (N + 1) + r];
   for (int mv = 0; mv < 15; ++mv) {
-    double acc = 0.0;
+    R acc = R(0);
     for (int cc = 0; cc < N; ++cc) acc += ops[O.Lint + (r - 1) * N + cc] * sV[mv * NP + cv_point<N>(d, q, cc)];
     Vf[mv] = acc;
   }
-  Prim<double> st = ns_prim(c, Uf);
-  double Fc[5], Fv[5];
+  Prim<R> st = ns_prim(c, Uf);
+  R Fc[5], Fv[5];
   ns_conv_dir(c, Uf, st, sv, Fc);
   ns_visc_dir(c, st, Vf, sv, Fv);
   for (int v = 0; v < 5; ++v) sG[(d * 5 + v) * NI + w] = Fc[v] - Fv[v];
 }
 
-template <int N>
-__global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restrict__ U, const double *__restrict__ T,
-                                                          const double *__restrict__ Sf,
-                                                          const double *__restrict__ Jinv,
-                                                          const double *__restrict__ ops, KArgs a, int compact,
-                                                          double *__restrict__ X, double *__restrict__ Part) {
+template <int N, typename R>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restrict__ U, const R *__restrict__ T,
+                                                          const R *__restrict__ Sf, const R *__restrict__ Jinv,
+                                                          const R *__restrict__ ops, KArgs a, int compact,
+                                                          R *__restrict__ X, R *__restrict__ Part) {
   using SM = CvnGradSmem<N>;
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = SM::NP, NF = SM::NF, NL = SM::NL, NI = SM::NI;
   extern __shared__ double smem_cvn[];
-  double *sS = smem_cvn + SM::S, *su = smem_cvn + SM::U, *sJ = smem_cvn + SM::J, *sT = smem_cvn + SM::T,
-         *sTn = smem_cvn + SM::TN, *sUF = smem_cvn + SM::UF, *sV = smem_cvn + SM::V, *sG = smem_cvn + SM::G;
+  R *base = reinterpret_cast<R *>(smem_cvn);
+  R *sS = base + SM::S, *su = base + SM::U, *sJ = base + SM::J, *sT = base + SM::T, *sTn = base + SM::TN,
+    *sUF = base + SM::UF, *sV = base + SM::V, *sG = base + SM::G;
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int t = tid; t < 9 * NL; t += nth) sS[t] = Sf[e * 9 * NL + t];
-  for (int t = tid; t < 5 * NP; t += nth) su[t] = U[e * 5 * NP + t];
+  for (int t = tid; t < 5 * NP; t += nth) su[t] = cv_in<R>(U[e * 5 * NP + t], a.U0[t / NP]);
   for (int t = tid; t < NP; t += nth) sJ[t] = Jinv[e * NP + t];
   __syncthreads();
   // own traces (from the state) and the neighbours'
   for (int t = tid; t < 30 * NF; t += nth) {
     const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF, d = f >> 1, s = f & 1;
-    sT[t] = cv_trace<N>(ops, su + v * NP, d, s, q);
+    R x[N];
+#pragma unroll
+    for (int cc = 0; cc < N; ++cc) x[cc] = su[v * NP + cv_point<N>(d, q, cc)];
+    sT[t] = cv_dot_end<N>(ops, x, s);
     sTn[t] = T[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
   }
   __syncthreads();
   // continuous solution of every variable at the flux points of every family
   for (int t = tid; t < 15 * NL; t += nth) {
     const int d = t / (5 * NL), w = t % (5 * NL), v = w / NL, l = w % NL, q = l / (N + 1), r = l % (N + 1);
-    double val;
+    R val;
     if (r == 0 || r == N) {
       const int f = 2 * d + (r == N ? 1 : 0);
       val = cvn_hat(sT, sTn, f, (f * 5 + v) * NF + q);
     } else {
-      val = 0.0;
+      val = R(0);
       for (int c = 0; c < N; ++c) val += ops[O.Lint + (r - 1) * N + c] * su[v * NP + cv_point<N>(d, q, c)];
     }
     sUF[t] = val;
@@ -454,11 +480,11 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
   // gradient of every variable at the solution points
   for (int t = tid; t < 15 * NP; t += nth) {
     const int mv = t / NP, pt = t % NP, m = mv / 5, v = mv % 5;
-    double acc = 0.0;
+    R acc = R(0);
     for (int d = 0; d < 3; ++d) {
       int q, c;
       cv_line_of<N>(pt, d, q, c);
-      double dd = 0.0;
+      R dd = R(0);
       for (int r = 0; r <= N; ++r)
         dd += ops[O.M + c * (N + 1) + r] *
               (sUF[(d * 5 + v) * NL + q * (N + 1) + r] * sS[((d * NF + q) * (N + 1) + r) * 3 + m]);
@@ -467,7 +493,7 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
     sV[t] = sJ[pt] * acc;
   }
   __syncthreads();
-  const NsConst<double> c(a);
+  const NsConst<R> c(a);
   // one list of work items: the element's half of the common flux at every
   // face point, then G_d at the interior flux points of family d
   for (int t = tid; t < 6 * NF + 3 * NI; t += nth) {
@@ -476,53 +502,53 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
       continue;
     }
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
-    const double *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
-    const double sv[3] = {srow[0], srow[1], srow[2]};
+    const R *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
+    const R sv[3] = {srow[0], srow[1], srow[2]};
     // one-sided (compact: the family-d solution of face s keeps the own
     // trace at the other face) or standard face values of the gradient
     const int so = 1 - s, rend = so == 0 ? 0 : N;
-    const double *sro = sS + ((d * NF + q) * (N + 1) + rend) * 3;
-    double Vf[15];
+    const R *sro = sS + ((d * NF + q) * (N + 1) + rend) * 3;
+    R Vf[15];
     for (int mv = 0; mv < 15; ++mv) {
       const int m = mv / 5, v = mv % 5;
-      double corr = 0.0;
+      R corr = R(0);
       if (compact) {
         const int idx = ((2 * d + so) * 5 + v) * NF + q;
         corr = (sT[idx] - cvn_hat(sT, sTn, 2 * d + so, idx)) * sro[m];
       }
-      double acc = 0.0;
+      R acc = R(0);
       for (int cc = 0; cc < N; ++cc) {
         const int pt = cv_point<N>(d, q, cc);
-        double g = sV[mv * NP + pt];
+        R g = sV[mv * NP + pt];
         if (compact) g += sJ[pt] * (ops[O.M + cc * (N + 1) + rend] * corr);
         acc += ops[O.Lend + s * N + cc] * g;
       }
       Vf[mv] = acc;
     }
-    double UL[5], UR[5], Uh[5];
+    R UL[5], UR[5], Uh[5];
     for (int v = 0; v < 5; ++v) {
       const int idx = (f * 5 + v) * NF + q;
       UL[v] = s == 0 ? sTn[idx] : sT[idx];
       UR[v] = s == 0 ? sT[idx] : sTn[idx];
       Uh[v] = cvn_hat(sT, sTn, f, idx);
     }
-    const double nrm = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
-    const double nv[3] = {sv[0] / nrm, sv[1] / nrm, sv[2] / nrm};
-    double Fr[5], Fv[5];
+    const R nrm = fsqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+    const R nv[3] = {sv[0] / nrm, sv[1] / nrm, sv[2] / nrm};
+    R Fr[5], Fv[5];
     ns_roe_dir(c, UL, UR, nv, Fr);
-    Prim<double> st = ns_prim(c, Uh);
+    Prim<R> st = ns_prim(c, Uh);
     ns_visc_dir(c, st, Vf, sv, Fv);
-    for (int v = 0; v < 5; ++v) X[(e * 6 + f) * 5 * NF + v * NF + q] = 0.5 * (nrm * Fr[v]) - 0.5 * Fv[v];
+    for (int v = 0; v < 5; ++v) X[(e * 6 + f) * 5 * NF + v * NF + q] = R(0.5) * (nrm * Fr[v]) - R(0.5) * Fv[v];
   }
   __syncthreads();
   // their part of the divergence
   for (int t = tid; t < 5 * NP; t += nth) {
     const int v = t / NP, pt = t % NP;
-    double acc = 0.0;
+    R acc = R(0);
     for (int d = 0; d < 3; ++d) {
       int q, cc;
       cv_line_of<N>(pt, d, q, cc);
-      double dd = 0.0;
+      R dd = R(0);
       for (int r = 1; r < N; ++r) dd += ops[O.M + cc * (N + 1) + r] * sG[(d * 5 + v) * NI + q * (N - 1) + r - 1];
       acc += dd;
     }
@@ -530,35 +556,41 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(kCvnThreads) k_cvn_face(const double *__restrict__ X,
-                                                          const double *__restrict__ Part,
-                                                          const double *__restrict__ Jinv,
-                                                          const double *__restrict__ ops, KArgs a,
+// With the reference state removed, the momentum fluxes carry P - p0 and
+// P0div holds -J^-1 sum_d D_d (p0 S_dm) per element (three n^3 blocks, the
+// divergence of the removed constant flux F_c(U0) . S_d, zero wherever the
+// metric identities hold discretely); adding it back keeps the equations of
+// the full-pressure discretisation on every mesh.
+template <int N, typename R>
+__global__ void __launch_bounds__(kCvnThreads) k_cvn_face(const R *__restrict__ X, const R *__restrict__ Part,
+                                                          const R *__restrict__ Jinv, const R *__restrict__ ops,
+                                                          KArgs a, const R *__restrict__ P0div,
                                                           double *__restrict__ dudt) {
   constexpr OpsLayout O = ops_layout(N);
   constexpr int NP = N * N * N, NF = N * N;
-  __shared__ double sGf[30 * NF];
+  __shared__ R sGf[30 * NF];
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int t = tid; t < 30 * NF; t += nth) {
     const int f = t / (5 * NF), w = t % (5 * NF), d = f >> 1, s = f & 1;
-    const double own = X[e * 30 * NF + t];
-    const double oth = X[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
+    const R own = X[e * 30 * NF + t];
+    const R oth = X[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
     sGf[t] = s == 0 ? oth + own : own + oth;
   }
   __syncthreads();
   for (int t = tid; t < 5 * NP; t += nth) {
     const int v = t / NP, pt = t % NP;
-    double acc = Part[e * 5 * NP + t];
+    R acc = Part[e * 5 * NP + t];
     for (int d = 0; d < 3; ++d) {
       int q, cc;
       cv_line_of<N>(pt, d, q, cc);
       acc += ops[O.M + cc * (N + 1)] * sGf[((2 * d) * 5 + v) * NF + q] +
              ops[O.M + cc * (N + 1) + N] * sGf[((2 * d + 1) * 5 + v) * NF + q];
     }
-    dudt[e * 5 * NP + t] = -Jinv[e * NP + pt] * acc;
+    double r = (double)(-Jinv[e * NP + pt] * acc);
+    if (P0div && v >= 1 && v <= 3) r += (double)P0div[(e * 3 + v - 1) * NP + pt];
+    dudt[e * 5 * NP + t] = r;
   }
 }
 

@@ -219,7 +219,7 @@ class SD:
                 "energy": d.energy, "umax": d.umax, "nonfinite": bool(d.nonfinite), "smax": d.smax}
 
     def set_geometry(self, nodes):
-        """Curvilinear elements (3-D diffusion or Navier-Stokes, FP64): nodes[e][c][b][a][3],
+        """Curvilinear elements (3-D diffusion or Navier-Stokes, FP64 or FP32): nodes[e][c][b][a][3],
         q + 1 equispaced nodes per direction of every element (q = 1 or 2)."""
         import numpy as np
         nodes = np.ascontiguousarray(nodes, dtype=np.float64)

@@ -43,9 +43,11 @@ def test_mlp_forward_matches_reference(torch_cuda, shape, B):
     print(f"forward {shape} B={B}: max error {err.max() / scale:.2e} of max|y|, "
           f"{np.mean(err < 1e-5 * scale):.5f} within 1e-5, {np.mean(err < 1e-4 * scale):.5f} within 1e-4", flush=True)
     # products differ by FP32 accumulation only; a BF16 rounding of an
-    # activation taken on the other side of a tie may move a few outputs
-    assert np.mean(err < 1e-4 * scale) > 0.999
-    assert err.max() < 2e-2 * scale
+    # activation taken on the other side of a tie moves a few outputs by up to
+    # ~1e-4 of max|y| (tests/test_oracle_mlp.py shows the same with FP32 sums
+    # in the reference); measured 5.6e-5
+    assert np.mean(err < 1e-5 * scale) > 0.99
+    assert err.max() < 2e-4 * scale
 
 
 @pytest.mark.parametrize("shape,B", [((64, 32, 48), 100), ((64, 32, 48), 1), ((64, 32, 48), 37),
@@ -161,13 +163,14 @@ def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
             assert rej == len(U)
             ref = Ro
         # same bar as the forward test: BF16 roundings of activations may fall
-        # on the other side of a tie for a few values
+        # on the other side of a tie for a few values (measured at most 1.0e-6
+        # of max|C| here)
         d = np.abs(R - ref)
         ys = out_scale * np.abs(Yo).max()
         print(f"closure in solver n_h={n_h} out_scale={out_scale:g} max_ratio={max_ratio:g}: max error "
               f"{(d.max() - 1e-11 * np.abs(Ro).max()) / ys:.2e} of max|C|", flush=True)
-        assert d.max() < 2e-2 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()
-        assert np.mean(d < 1e-4 * out_scale * np.abs(Yo).max() + 1e-11 * np.abs(Ro).max()) > 0.999
+        assert d.max() < 2e-4 * ys + 1e-11 * np.abs(Ro).max()
+        assert np.mean(d < 1e-5 * ys + 1e-11 * np.abs(Ro).max()) > 0.99
         sd.close()
 
 

@@ -1,8 +1,9 @@
-"""Curvilinear hexahedra on the GPU (3-D diffusion, FP64) against the
-curvilinear reference: right-hand sides on affine, rotated (full S) and
+"""Curvilinear hexahedra on the GPU (3-D diffusion, FP64 and FP32) against
+the curvilinear reference: right-hand sides on affine, rotated (full S) and
 curved meshes, ragged element counts, p = 1..6, both schemes, with and
-without the interior penalty; RK4 and SSP-RK(5,4) steps; argument checks.  Bar: 1e-12 of max|R| (the metric terms
-are computed independently on both sides, each to a few ulps)."""
+without the interior penalty; RK4 and SSP-RK(5,4) steps; argument checks.
+Bar: FP64 1e-12 of max|R| (the metric terms are computed independently on
+both sides, each to a few ulps); FP32 2e-5."""
 import math
 
 import numpy as np
@@ -24,10 +25,11 @@ def torch_cuda():
     return torch
 
 
-def make(torch, nel, p, scheme, Xg, nu=0.7, **kw):
+def make(torch, nel, p, scheme, Xg, nu=0.7, precision="fp64", **kw):
     from paper_2608_09615_amd import SD
-    print(f"[curv] nel={nel} p={p} {scheme} q={Xg.shape[1] - 1}", flush=True)
-    sd = SD(nel, p, scheme=scheme, physics="diffusion", precision="fp64", lo=[0.0] * 3, hi=[1.0] * 3, nu=nu, **kw)
+    print(f"[curv] nel={nel} p={p} {scheme} {precision} q={Xg.shape[1] - 1}", flush=True)
+    sd = SD(nel, p, scheme=scheme, physics="diffusion", precision=precision, lo=[0.0] * 3, hi=[1.0] * 3, nu=nu,
+            **kw)
     sd.set_geometry(Xg)
     return sd
 
@@ -55,6 +57,32 @@ def test_curvilinear_rhs_parity(torch_cuda, scheme, p):
             err = np.abs(R - Ro).max() / np.abs(Ro).max()
             print(f"  {name} {nel}: {err:.2e}")
             assert err < 1e-12, (name, nel, err)
+
+
+# FP32: the metric terms, the contractions over n + 1 <= 8 terms and the
+# fluxes in single precision on O(1) data; the bar is a few hundred FP32 ulps
+# of the largest value, as on Cartesian meshes
+FP32_TOL = 2e-5
+
+
+@pytest.mark.parametrize("scheme", ["br1", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_curvilinear_rhs_parity_fp32(torch_cuda, scheme, p):
+    """The FP32 path (metric terms stored and used in FP32) against the
+    reference on the affine, rotated and curved meshes, with and without
+    the interior penalty."""
+    for nel in ((3, 2, 4), (1, 3, 2)):
+        E, n = int(np.prod(nel)), p + 1
+        u = np.random.Generator(np.random.PCG64(10 * p + E)).normal(size=(E, n, n, n))
+        for name, Xg in meshes(nel).items():
+            for eta in (0.0, 0.4):
+                sd = make(torch_cuda, nel, p, scheme, Xg, precision="fp32", eta_ip=eta)
+                R = sd.rhs(torch_cuda.from_numpy(u[:, None]).to("cuda")).cpu().numpy()[:, 0]
+                sd.close()
+                Ro = C.rhs(u, nel, Xg, p, scheme, nu=0.7, eta_ip=eta)
+                err = np.abs(R - Ro).max() / np.abs(Ro).max()
+                print(f"  fp32 {name} {nel} eta={eta}: {err:.2e}")
+                assert err < FP32_TOL, (name, nel, eta, err)
 
 
 @pytest.mark.parametrize("scheme", ["br1", "compact"])
@@ -132,9 +160,11 @@ def test_curvilinear_argument_checks(torch_cuda):
     nel, p = (2, 2, 2), 2
     good = W.mesh_nodes(nel, *BOX, q=1)
     lo, hi = W.tgv_domain()
-    for kw in (dict(physics="ns", precision="fp32", lo=lo, hi=hi),
-               dict(physics="diffusion", precision="fp32", lo=lo, hi=hi)):
-        sd = SD(nel, p, scheme="compact", **kw)
+    # a precision without a curvilinear path, and a 1-D context (8 elements,
+    # as many as the node array holds)
+    for ne, kw in ((nel, dict(physics="ns", precision="bf16x3", lo=lo, hi=hi)),
+                   ([8], dict(physics="diffusion", lo=[0.0], hi=[1.0]))):
+        sd = SD(ne, p, scheme="compact", **kw)
         with pytest.raises(SDError):
             sd.set_geometry(good)
         sd.close()

@@ -128,3 +128,42 @@ def test_weighted_mse_definition_and_gradient():
         ym[i, j] -= h
         fd = (M.mse(yp, t, w)[0] - M.mse(ym, t, w)[0]) / (2 * h)
         assert gw[i, j] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+
+
+def test_fp32_sums_flip_a_few_bf16_activation_roundings():
+    """Why the GPU forward can differ from the reference by more than its
+    FP32 sums alone would suggest: evaluated with FP32 sums (as the matrix
+    cores accumulate) instead of exact ones, the same BF16 network rounds a
+    few layer activations to the neighbouring BF16 value, and each such flip
+    moves some outputs by ~1e-5 to 1e-4 of max|y|; without the BF16 roundings
+    the FP32 sums alone stay near 1e-6.  320-128-320 network, 1000 samples,
+    the seeds of the GPU forward test."""
+    n_in, n_h, n_out, B = 320, 128, 320, 1000
+    p = M.init_params(n_in, n_h, n_out, 1)
+    rng = np.random.Generator(np.random.PCG64(101))
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(size=p[k].shape) * 0.1
+    p = M.unflatten(M.flatten(p).astype(np.float32).astype(np.float64), n_in, n_h, n_out)
+    x = np.random.Generator(np.random.PCG64(2)).normal(size=(B, n_in)).astype(np.float32).astype(np.float64)
+    y, cache = M.forward(p, x, bf16=True)
+    f32 = np.float32
+
+    def layers(rnd):
+        W1, W2, W3 = (rnd(p[k]) for k in ("W1", "W2", "W3"))
+        a0 = rnd(x)
+        z1 = (a0.astype(f32) @ W1.T.astype(f32) + p["b1"].astype(f32)).astype(np.float64)
+        a1 = rnd(M.gelu(z1))
+        z2 = (a1.astype(f32) @ W2.T.astype(f32) + p["b2"].astype(f32)).astype(np.float64)
+        a2 = rnd(M.gelu(z2))
+        return (a2.astype(f32) @ W3.T.astype(f32) + p["b3"].astype(f32)).astype(np.float64), a1, a2
+
+    y32, a1, a2 = layers(M.bf16_round)
+    flips = int(np.sum(a1 != cache["a1"]) + np.sum(a2 != cache["a2"]))
+    err = np.abs(y32 - y) / np.abs(y).max()
+    assert 0 < flips < 1e-3 * (a1.size + a2.size)
+    assert 1e-5 < err.max() < 2e-4
+    assert np.mean(err < 1e-5) > 0.99
+    # the same FP32 sums without any BF16 rounding
+    yx, _ = M.forward(p, x)
+    yx32, _, _ = layers(lambda a: np.asarray(a, dtype=np.float64))
+    assert np.abs(yx32 - yx).max() / np.abs(yx).max() < 1e-5
