@@ -63,6 +63,8 @@ def parse():
                          "JSON line")
     ap.add_argument("--bloch-theta", type=int, default=1 << 16,
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
+    ap.add_argument("--developed", type=int, default=1,
+                    help="also time the RHS on the state advanced to t* = 9 (0: skip it)")
     ap.add_argument("--curv-nel", type=int, default=32,
                     help="elements per direction of the curvilinear workloads (0: skip them)")
     ap.add_argument("--curv-p", type=int, default=3, help="degree of the curvilinear workloads")
@@ -181,6 +183,35 @@ def run_path(torch, W, args, precision, U0, dt):
         "nonfinite": diag["nonfinite"],
     }
     sd.close()
+    return out
+
+
+def developed_state_bench(torch, W, args, U0, dt, t_dev=9.0):
+    """Throughput on a developed flow: the workload's state advanced in FP32
+    to t* = t_dev (near the enstrophy peak at Re = 1600), then the same timed
+    RK4 steps as the headline on that state, FP32 and FP64; the Roe branches
+    (and so the work) depend on the values, nothing else does."""
+    from paper_2608_09615_amd import SD
+    lo, hi = W.tgv_domain()
+    nel = (args.nel,) * 3
+    sd = SD(nel, args.p, scheme=args.scheme, physics="ns", precision="fp32", lo=lo, hi=hi, Re=args.Re, Ma=0.1,
+            Pr=0.71, gamma=1.4)
+    u = torch.from_numpy(U0).to("cuda")
+    nst = int(math.ceil(t_dev / dt))
+    t0 = time.perf_counter()
+    for k in range(nst):
+        sd.rk_step(u, t_dev / nst)
+        if k % 2000 == 1999:
+            torch.cuda.synchronize()
+            print(f"bench: developed state t={(k + 1) * t_dev / nst:.2f}", file=sys.stderr, flush=True)
+    d = sd.diagnostics(u)
+    sd.close()
+    wall = time.perf_counter() - t0
+    Ud = u.cpu().numpy()
+    out = {"t": t_dev, "steps_to_reach": nst, "wall_s_to_reach": wall, "ke": d["ke"], "enstrophy": d["enstrophy"]}
+    for precision in ("fp32", "fp64"):
+        r = run_path(torch, W, args, precision, Ud, dt)
+        out[precision] = {"value": r["gdofs"], "ms_per_step": r["ms_per_step"], "rhs_ms": r["rhs_ms_avg"]}
     return out
 
 
@@ -652,6 +683,8 @@ def main():
         rec["bf16x3"] = {"value": rbf["gdofs"], "ms_per_step": rbf["ms_per_step"], "dtype": "f32+bf16x3",
                          "roofline": roof(rbf, PEAK_FP32_TFLOPS, "k_rhs_ns", "bf16x3"),
                          "mfma": mfma_use(args, "bf16x3", rbf["rhs_ms_avg"])}
+    if args.developed:
+        rec["developed_state"] = developed_state_bench(torch, W, args, U0, dt)
     if args.bloch_theta > 0:
         rec["bloch"] = bloch_bench(torch, args)
     if args.curv_nel > 0:
