@@ -510,11 +510,11 @@ def training_bench(torch, args, p=3, hidden=128, batch=1024, steps=200):
 
 def closure_record():
     """The trained closure's errors and speedup on the held-out seed(s) of the
-    64^3 -> 16^3 case (profiles/closure_64to16_p3_seed*.json, written by
+    64^3 -> 16^3 case (profiles/closure_64to16_p3_*seed*.json, written by
     paper_2608_09615_amd.closure; the command is in each record)."""
     import glob
     out = []
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "closure_64to16_p3_seed*.json"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "closure_64to16_p3_*seed*.json"))):
         with open(path) as f:
             rec = json.load(f)
         post = rec["a_posteriori"]

@@ -383,8 +383,8 @@ template <int N>
 struct CvnGradSmem {
   static constexpr int NP = N * N * N, NF = N * N, NL = (N + 1) * NF, NI = (N - 1) * NF;
   static constexpr int S = 0, U = S + 9 * NL, J = U + 5 * NP, T = J + NP, TN = T + 30 * NF, UF = TN + 30 * NF,
-                       V = UF + 15 * NL, G = V + 15 * NP;
-  static constexpr int TOTAL = G + 15 * NI;
+                       V = UF + 15 * NL, G = V + 15 * NP, VF = G + 15 * NI;
+  static constexpr int TOTAL = VF + 90 * NF;
 };
 
 template <int N, typename R>
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
   extern __shared__ double smem_cvn[];
   R *base = reinterpret_cast<R *>(smem_cvn);
   R *sS = base + SM::S, *su = base + SM::U, *sJ = base + SM::J, *sT = base + SM::T, *sTn = base + SM::TN,
-    *sUF = base + SM::UF, *sV = base + SM::V, *sG = base + SM::G;
+    *sUF = base + SM::UF, *sV = base + SM::V, *sG = base + SM::G, *sVf = base + SM::VF;
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -493,6 +493,27 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
     sV[t] = sJ[pt] * acc;
   }
   __syncthreads();
+  // one-sided (compact: the family-d solution of face s keeps the own trace
+  // at the other face) or standard face values of every gradient component,
+  // sVf[f][mv][q], one item per value
+  for (int t = tid; t < 90 * NF; t += nth) {
+    const int f = t / (15 * NF), w = t % (15 * NF), mv = w / NF, q = w % NF, d = f >> 1, s = f & 1;
+    const int m = mv / 5, v = mv % 5, so = 1 - s, rend = so == 0 ? 0 : N;
+    R corr = R(0);
+    if (compact) {
+      const int idx = ((2 * d + so) * 5 + v) * NF + q;
+      corr = (sT[idx] - cvn_hat(sT, sTn, 2 * d + so, idx)) * sS[((d * NF + q) * (N + 1) + rend) * 3 + m];
+    }
+    R acc = R(0);
+    for (int cc = 0; cc < N; ++cc) {
+      const int pt = cv_point<N>(d, q, cc);
+      R g = sV[mv * NP + pt];
+      if (compact) g += sJ[pt] * (ops[O.M + cc * (N + 1) + rend] * corr);
+      acc += ops[O.Lend + s * N + cc] * g;
+    }
+    sVf[t] = acc;
+  }
+  __syncthreads();
   const NsConst<R> c(a);
   // one list of work items: the element's half of the common flux at every
   // face point, then G_d at the interior flux points of family d
@@ -504,27 +525,8 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
     const R *srow = sS + ((d * NF + q) * (N + 1) + (s ? N : 0)) * 3;
     const R sv[3] = {srow[0], srow[1], srow[2]};
-    // one-sided (compact: the family-d solution of face s keeps the own
-    // trace at the other face) or standard face values of the gradient
-    const int so = 1 - s, rend = so == 0 ? 0 : N;
-    const R *sro = sS + ((d * NF + q) * (N + 1) + rend) * 3;
     R Vf[15];
-    for (int mv = 0; mv < 15; ++mv) {
-      const int m = mv / 5, v = mv % 5;
-      R corr = R(0);
-      if (compact) {
-        const int idx = ((2 * d + so) * 5 + v) * NF + q;
-        corr = (sT[idx] - cvn_hat(sT, sTn, 2 * d + so, idx)) * sro[m];
-      }
-      R acc = R(0);
-      for (int cc = 0; cc < N; ++cc) {
-        const int pt = cv_point<N>(d, q, cc);
-        R g = sV[mv * NP + pt];
-        if (compact) g += sJ[pt] * (ops[O.M + cc * (N + 1) + rend] * corr);
-        acc += ops[O.Lend + s * N + cc] * g;
-      }
-      Vf[mv] = acc;
-    }
+    for (int mv = 0; mv < 15; ++mv) Vf[mv] = sVf[(f * 15 + mv) * NF + q];
     R UL[5], UR[5], Uh[5];
     for (int v = 0; v < 5; ++v) {
       const int idx = (f * 5 + v) * NF + q;
