@@ -63,6 +63,8 @@ def parse():
                          "JSON line")
     ap.add_argument("--bloch-theta", type=int, default=1 << 16,
                     help="wavenumbers of the Bloch / combined-mode sweep (0: skip it)")
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time the Re = 5000 workloads at 64^3 p = 3 and 43^3 p = 5 (0: skip them)")
     ap.add_argument("--developed", type=int, default=1,
                     help="also time the RHS on the state advanced to t* = 9 (0: skip it)")
     ap.add_argument("--curv-nel", type=int, default=32,
@@ -183,6 +185,30 @@ def run_path(torch, W, args, precision, U0, dt):
         "nonfinite": diag["nonfinite"],
     }
     sd.close()
+    return out
+
+
+def large_bench(torch, W, args, steps=10):
+    """The Re = 5000 Taylor-Green workloads at full size, 64^3 elements at
+    p = 3 and 43^3 at p = 5 (about 17 M solution points each), both schemes,
+    FP32, FP64 and BF16x3: GDOF/s per RK stage from the same timed RK4 steps
+    as the headline (the convective step of each mesh)."""
+    out = {}
+    for nel, p in ((64, 3), (43, 5)):
+        a = argparse.Namespace(**{**vars(args), "nel": nel, "p": p, "Re": 5000.0, "steps": steps, "warmup": 2,
+                                  "eta_ip": 0.0, "integrator": "rk4"})
+        U0 = W.tgv_state((nel,) * 3, p)
+        h = 2 * math.pi / nel
+        dt = 0.3 * h / ((p + 1) * (1.0 + math.sqrt(1.4 * (1.0 / 1.4 / 0.01))))
+        rec = {}
+        for scheme in ("compact", "br1"):
+            a.scheme = scheme
+            for precision in ("fp32", "fp64", "bf16x3"):
+                r = run_path(torch, W, a, precision, U0, dt)
+                rec[f"{scheme}_{precision}"] = {"value": r["gdofs"], "rhs_ms": r["rhs_ms_avg"]}
+        out[f"tgv{nel}_p{p}"] = {"workload": f"TGV Re=5000 Ma=0.1 {nel}^3 hex p={p}",
+                                 "dof": nel ** 3 * (p + 1) ** 3, "gdofs": rec}
+        print(f"bench: {nel}^3 p={p} done", file=sys.stderr, flush=True)
     return out
 
 
@@ -685,6 +711,8 @@ def main():
                          "mfma": mfma_use(args, "bf16x3", rbf["rhs_ms_avg"])}
     if args.developed:
         rec["developed_state"] = developed_state_bench(torch, W, args, U0, dt)
+    if args.large:
+        rec["large"] = large_bench(torch, W, args)
     if args.bloch_theta > 0:
         rec["bloch"] = bloch_bench(torch, args)
     if args.curv_nel > 0:
