@@ -299,10 +299,22 @@ def cpu_baseline(W, args, U0, R_gpu64=None):
     reps1, sec1, _ = timed(1, sel[:n1], max(2.0, args.cpu_seconds / 4))
     dof_el = (args.p + 1) ** 3
     out = {"value": reps * n * dof_el / sec / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+           "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()},
            "sample": f"{reps} RHS evaluations on the first {n} of {ne} elements of the same TGV state "
                      f"({sec:.1f} s wall, OpenMP over elements)",
            "single_thread": {"value": reps1 * n1 * dof_el / sec1 / 1e9, "unit": "GDOF/s", "cores": 1,
                              "sample": f"{reps1} RHS evaluations on the first {n1} elements ({sec1:.1f} s wall)"}}
+    # the closure network's forward pass (320-128-128-320, BF16 roundings,
+    # exact sums): the reference on one batch of the coarse mesh's elements
+    from oracle import mlp as M
+    nve = 5 * dof_el
+    pm = M.init_params(nve, 128, nve, 0)
+    xb = np.random.Generator(np.random.PCG64(5)).normal(size=(4096, nve))
+    t0 = time.perf_counter()
+    M.forward(pm, xb, bf16=True)
+    tf = time.perf_counter() - t0
+    out["closure_forward"] = {"value": 4096 / tf, "unit": "elements/s",
+                              "sample": f"one forward pass of 4096 elements ({tf:.2f} s, numpy FP64, BLAS threads)"}
     if R_gpu64 is not None:
         Ro = np.asarray(Ro).reshape(n, 5, -1)
         Rop = np.asarray(Rop).reshape(n, 5, -1)
@@ -317,6 +329,57 @@ def cpu_baseline(W, args, U0, R_gpu64=None):
             "within_bar": all(e < max(1e-12, 4.0 * x) for e, x in zip(err, sens)),
             "sample": f"first {n} elements, the workload's initial state (max|R| per variable: "
                       + ", ".join(f"{x:.2e}" for x in scale) + ")"}
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oned_bench(torch, args, p=3, N=16):
+    """Whole run of the 1-D diffusion case (u_t = u_xx on [0, 2 pi], N
+    elements, p = 3, u0 = sin x, RK4 with dt = 1 / ceil(1 / (0.05 h^2 /
+    (p+1)^2)) to t = 1, both schemes, FP64) on the GPU and with the oracle
+    on one host thread, and the error against exp(-t) sin x.  The case is
+    64 solution points: the GPU run is bound by its launches."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd import workloads as W
+    h = 2 * math.pi / N
+    nst = int(math.ceil(1.0 / (0.05 * h * h / (p + 1) ** 2)))
+    dt = 1.0 / nst
+    x = W.points_1d(N, p, 0.0, 2 * math.pi)
+    u0 = np.sin(x)
+    out = {"config": f"1-D diffusion, {N} elements, p={p}, RK4 {nst} steps to t=1, FP64"}
+    for scheme in ("compact", "br1"):
+        sd = SD([N], p, scheme=scheme, physics="diffusion", precision="fp64", lo=[0.0], hi=[2 * math.pi], nu=1.0)
+        u = torch.from_numpy(np.ascontiguousarray(u0[:, None, :])).to("cuda")
+        sd.rk_step(u, dt)
+        torch.cuda.synchronize()
+        u.copy_(torch.from_numpy(np.ascontiguousarray(u0[:, None, :])))
+        t0 = time.perf_counter()
+        for _ in range(nst):
+            sd.rk_step(u, dt)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        ug = u.cpu().numpy()[:, 0, :]
+        sd.close()
+        t0 = time.perf_counter()
+        uo = O.rk4_1d(u0, p, 0.0, 2 * math.pi, dt, nst, scheme=scheme)
+        to = time.perf_counter() - t0
+        ex = math.exp(-1.0) * np.sin(x)
+        out[scheme] = {"gpu_s": tg, "oracle_1thread_s": to, "gpu_max_err": float(np.abs(ug - ex).max()),
+                       "oracle_max_err": float(np.abs(uo - ex).max()),
+                       "gpu_vs_oracle": float(np.abs(ug - uo).max())}
     return out
 
 
@@ -711,6 +774,7 @@ def main():
                          "mfma": mfma_use(args, "bf16x3", rbf["rhs_ms_avg"])}
     if args.developed:
         rec["developed_state"] = developed_state_bench(torch, W, args, U0, dt)
+
     if args.large:
         rec["large"] = large_bench(torch, W, args)
     if args.bloch_theta > 0:
@@ -726,6 +790,7 @@ def main():
         rec["closure_training"] = training_bench(torch, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W, args, U0, fp64_rhs(torch, args, U0))
+        rec["cpu_baseline"]["oned_whole_run"] = oned_bench(torch, args)
     print(json.dumps(rec), flush=True)
 
 
