@@ -244,3 +244,33 @@ def test_curvilinear_ns_argument_checks(torch_cuda):
     sd.close()
     Ro, sens = reference(U, (2, 2, 2), good, 2, "compact")
     check(R, Ro, sens, "after the rejected calls")
+
+
+def test_closure_and_curvilinear_geometry_exclude_each_other(torch_cuda):
+    """The learned closure is built for Cartesian elements: arming it on a
+    curvilinear context, or giving a closure context a geometry, is rejected
+    and leaves the context as it was."""
+    from paper_2608_09615_amd import SD
+    from paper_2608_09615_amd.sd import Mlp, SDError
+    nel, p = (2, 2, 2), 3
+    good = W.mesh_nodes(nel, *BOX, q=1)
+    net = Mlp(5 * (p + 1) ** 3, 32, 5 * (p + 1) ** 3)
+    norm = ([0.0] * 5, [1.0] * 5, [1e-3] * 5)
+    U = W.perturbed_tgv_state(nel, p, seed=2, noise=1e-2)
+    sd = make(torch_cuda, nel, p, "compact", good)
+    with pytest.raises(SDError):
+        sd.closure_set(net, *norm)
+    R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+    sd.close()
+    Ro, sens = reference(U, nel, good, p, "compact")
+    check(R, Ro, sens, "curvilinear after the rejected closure")
+    lo, hi = W.tgv_domain()
+    sd = SD(nel, p, scheme="compact", physics="ns", lo=lo, hi=hi, Re=RE)
+    sd.closure_set(net, *norm)
+    with pytest.raises(SDError):
+        sd.set_geometry(good)
+    sd.closure_set(None)
+    sd.set_geometry(good)
+    R = sd.rhs(torch_cuda.from_numpy(U).to("cuda")).cpu().numpy()
+    sd.close()
+    check(R, Ro, sens, "geometry after the closure was switched off")
