@@ -372,12 +372,25 @@ def oned_bench(torch, args, p=3, N=16):
         torch.cuda.synchronize()
         tg = time.perf_counter() - t0
         ug = u.cpu().numpy()[:, 0, :]
+        # the same run with the steps replayed from a captured HIP graph
+        # (256 steps per graph): the launches, not the kernels, bound it
+        u.copy_(torch.from_numpy(np.ascontiguousarray(u0[:, None, :])))
+        sd.rk_steps(u, dt, 257, graph_steps=256)
+        torch.cuda.synchronize()
+        u.copy_(torch.from_numpy(np.ascontiguousarray(u0[:, None, :])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sd.rk_steps(u, dt, nst, graph_steps=256)
+        torch.cuda.synchronize()
+        tgg = time.perf_counter() - t0
+        ugg = u.cpu().numpy()[:, 0, :]
         sd.close()
         t0 = time.perf_counter()
         uo = O.rk4_1d(u0, p, 0.0, 2 * math.pi, dt, nst, scheme=scheme)
         to = time.perf_counter() - t0
         ex = math.exp(-1.0) * np.sin(x)
-        out[scheme] = {"gpu_s": tg, "oracle_1thread_s": to, "gpu_max_err": float(np.abs(ug - ex).max()),
+        out[scheme] = {"gpu_s": tg, "gpu_graph_s": tgg, "graph_vs_eager": float(np.abs(ugg - ug).max()),
+                       "oracle_1thread_s": to, "gpu_max_err": float(np.abs(ug - ex).max()),
                        "oracle_max_err": float(np.abs(uo - ex).max()),
                        "gpu_vs_oracle": float(np.abs(ug - uo).max())}
     return out

@@ -176,6 +176,7 @@ class SD:
         self.shape = (self.ne, self.nv) + (self.n,) * dim
         self.params = prm
         self._ctx = ctypes.c_void_p()
+        self._graphs = {}
         stream = torch.cuda.current_stream().cuda_stream
         _check(L.sd_init(ctypes.byref(m), p, SCHEMES[scheme], ctypes.byref(prm), ctypes.c_void_p(stream),
                          ctypes.byref(self._ctx)))
@@ -206,6 +207,52 @@ class SD:
         self._check_state(u)
         self._stream()
         _check(load_library().sd_rk_step(self._ctx, ctypes.c_void_p(u.data_ptr()), float(dt)))
+        return u
+
+    def rk_steps(self, u, dt, nsteps, graph_steps=0):
+        """``nsteps`` steps of sd_rk_step on ``u`` (in place).  With
+        ``graph_steps`` > 0 the launches of ``graph_steps`` consecutive steps
+        are captured once into a HIP graph on a side stream and the graph is
+        replayed on the current stream (the first step runs eagerly, so that
+        every buffer the steps use exists before the capture; a remainder
+        runs eagerly too).  The results are those of the eager steps: the
+        graph replays the same kernels on the same buffers.  The graph is
+        kept with the context for later calls with the same state, step and
+        length; keep timing() off while steps are captured."""
+        import torch
+        nsteps = int(nsteps)
+        if graph_steps <= 0 or nsteps <= graph_steps:
+            for _ in range(nsteps):
+                self.rk_step(u, dt)
+            return u
+        self.rk_step(u, dt)
+        left = nsteps - 1
+        if left < graph_steps:
+            for _ in range(left):
+                self.rk_step(u, dt)
+            return u
+        # one graph per (state, step, graph length), kept with the context so
+        # that later calls replay it and no replay outlives its graph
+        key = (u.data_ptr(), float(dt), int(graph_steps))
+        graph = self._graphs.get(key)
+        if graph is None:
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(graph, stream=side):
+                    for _ in range(graph_steps):
+                        self.rk_step(u, dt)
+            torch.cuda.current_stream().wait_stream(side)
+            self._graphs[key] = graph
+        for _ in range(left // graph_steps):
+            graph.replay()
+        for _ in range(left % graph_steps):
+            self.rk_step(u, dt)
+        # the context's stream back to the one the replays ran on (its later
+        # calls, and sd_free's wait, follow them)
+        self._stream()
         return u
 
     def diagnostics(self, u, raise_nonfinite=False):
@@ -268,6 +315,12 @@ class SD:
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            if getattr(self, "_graphs", None):
+                # captured steps reference the context's buffers: let every
+                # replay finish, then drop the graphs before the buffers go
+                import torch
+                torch.cuda.synchronize()
+                self._graphs.clear()
             load_library().sd_free(self._ctx)
             self._ctx = ctypes.c_void_p()
 
