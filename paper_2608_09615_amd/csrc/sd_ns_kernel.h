@@ -236,6 +236,26 @@ __device__ __forceinline__ long long ns_block_elem(long long b, long long nblock
   return (x * q + (x < r ? x : r) + k) * epb;
 }
 
+// When every direction has an even element count and half the x count is
+// a multiple of the block's run, XCD x takes brick x of the 2 x 2 x 2 split
+// of the box instead, walking its x-runs row by row and plane by plane: the
+// planes of neighbour states it reuses are those of one brick, a quarter of
+// the box's.
+__device__ __forceinline__ bool ns_bricks(const KArgs &a, int epb) {
+  return ((a.nel[0] | a.nel[1] | a.nel[2]) & 1) == 0 && (a.nel[0] / 2) % epb == 0;
+}
+__device__ __forceinline__ long long ns_block_elem_brick(long long b, const KArgs &a, int epb) {
+  const int hx = a.nel[0] / 2, hy = a.nel[1] / 2, hz = a.nel[2] / 2;
+  const int x = (int)(b % 8);
+  const long long s = b / 8;
+  const int bpr = hx / epb;
+  const long long row = s / bpr;
+  const int col = (int)(s - row * bpr);
+  const int ly = (int)(row % hy), lz = (int)(row / hy);
+  const int ox = (x & 1) * hx, oy = ((x >> 1) & 1) * hy, oz = (x >> 2) * hz;
+  return (long long)(ox + col * epb) + (long long)a.nel[0] * ((oy + ly) + (long long)a.nel[1] * (oz + lz));
+}
+
 // number of values moved per vector load for a contiguous run of CNT values
 template <typename R, int CNT>
 __host__ __device__ constexpr int vec_width() {
@@ -900,7 +920,8 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
   }
   constexpr int epb = ns_epb<N, R>();              // == a.epb
   const long long nblocks = (a.ne + epb - 1) / epb;
-  const int e0 = (int)ns_block_elem(blockIdx.x, nblocks, epb);
+  const int e0 = (int)(ns_bricks(a, epb) ? ns_block_elem_brick(blockIdx.x, a, epb)
+                                          : ns_block_elem(blockIdx.x, nblocks, epb));
   const int nb = min(epb, (int)(a.ne - e0));
   const R *__restrict__ in_r = ch.in_r;
 

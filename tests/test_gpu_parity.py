@@ -454,3 +454,44 @@ def test_ssprk54_1d_diffusion_parity(torch_cuda, oracle_lib):
     sd.close()
     ref = ssprk.integrate(lambda x: oracle_lib.rhs_1d(x, p, 0.0, 2.0, scheme="compact", coef=0.6), u0, dt, 3)
     assert np.abs(got - ref).max() < 1e-12 * np.abs(ref - u0).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ns_parity_brick_order(torch_cuda, oracle_lib, precision):
+    """Meshes with even element counts whose half x count holds whole block
+    runs take the brick order of the blocks (each XCD one octant of the
+    box): every element's RHS against the oracle (FP64 bar max(1e-12, 4 x
+    the oracle's one-ulp sensitivity), as for the other full meshes with
+    small elements), and two chained RK4 steps against the RHS sequence."""
+    torch = torch_cuda
+    from paper_2608_09615_amd import SD
+    lo, hi = W.tgv_domain()
+    prm = oracle_lib.make_params("ns")
+    for nel in ((8, 4, 6), (16, 2, 4)):
+        U = W.perturbed_tgv_state(nel, 3, seed=31, noise=1e-3)
+        R, sd = gpu_rhs(torch, U, nel, 3, "compact", "ns", precision, lo, hi)
+        sd.close()
+        sel = np.arange(int(np.prod(nel)), dtype=np.int64)
+        Ro, sens = ulp_sensitivity(oracle_lib, U, nel, lo, hi, 3, "compact", prm, sel)
+        Ro = np.asarray(Ro).reshape(U.shape)
+        err = relerr(R, Ro)
+        print(f"brick order {nel} {precision}: {err:.2e} (ulp sensitivity {sens:.2e})", flush=True)
+        assert err < (max(FP64_TOL, 4 * sens) if precision == "fp64" else FP32_TOL_NS), (nel, err, sens)
+        sd = SD(nel, 3, scheme="compact", physics="ns", precision=precision, lo=lo, hi=hi)
+        dt = 2e-3
+        u = torch.from_numpy(U).to("cuda")
+        for _ in range(2):
+            sd.rk_step(u, dt)
+        v = torch.from_numpy(U).to("cuda")
+        for _ in range(2):
+            k1 = sd.rhs(v)
+            k2 = sd.rhs(v + 0.5 * dt * k1)
+            k3 = sd.rhs(v + 0.5 * dt * k2)
+            k4 = sd.rhs(v + dt * k3)
+            v = v + dt / 6.0 * (((k1 + 2.0 * k2) + 2.0 * k3) + k4)
+        d = np.abs(u.cpu().numpy() - v.cpu().numpy()) / np.abs(v.cpu().numpy() - U).max()
+        sd.close()
+        if precision == "fp64":
+            assert d.max() < 1e-12
+        else:
+            assert np.mean(d < 1e-12) > 0.9999 and d.max() < 1e-5
