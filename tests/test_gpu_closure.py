@@ -238,9 +238,11 @@ def test_closure_rk_step_matches_stage_sequence(torch_cuda, n_h):
     assert sd.closure_rejected() == 0
     d = (u - ref).abs().max().item()
     print(f"closure rk step n_h={n_h}: difference {d / (dt * Cmax):.2e} of dt max|C|", flush=True)
-    # stage states may differ in the last bit (fused multiply-add), which can
-    # move a BF16 rounding of a network input: bar as in the RHS test, times dt
-    assert d < dt * (2e-2 * Cmax + 1e-11 * R0.abs().max().item()) + 1e-14 * u0.abs().max().item()
+    # the stage states of the two sides may differ in the last bit (fused
+    # multiply-add); at this seeded state that moves no BF16 rounding of a
+    # network input (measured 2e-12 to 3.5e-11 of dt max|C|; a moved rounding
+    # would show as about 1e-3)
+    assert d < dt * (1e-8 * Cmax + 1e-11 * R0.abs().max().item()) + 1e-14 * u0.abs().max().item()
     # the closure does change the step, by far more than that bar
     assert (u - u_plain).abs().max().item() > 0.1 * dt * Cmax
     sd.close()
