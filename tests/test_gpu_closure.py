@@ -128,10 +128,11 @@ def test_filter_matches_reference(torch_cuda, ratio, p, nelc):
 def test_closure_in_solver(torch_cuda, oracle_lib, n_h, nel):
     """R_closure = R_plain + out_scale * net(normalised u) per element; a
     correction larger than max_ratio R is discarded for that element, and
-    max_ratio = 0 keeps every finite correction.  12 and 20 elements: one
-    padded block, and a full block plus a ragged one, of the single-launch
-    kernel (256 hidden units: its variant that reads the later layers'
-    weights layer by layer); 48 hidden units take the layer-by-layer path."""
+    max_ratio = 0 keeps every finite correction.  128 and 256 hidden units
+    run the single-launch kernel (20 and 18 elements: a full block plus a
+    ragged one; 256 hidden units: its variant that reads the later layers'
+    weights layer by layer); 32 and 48 hidden units take the layer-by-layer
+    path."""
     print(f"[closure in solver] n_h={n_h} nel={nel}", flush=True)
     torch = torch_cuda
     from paper_2608_09615_amd import SD
