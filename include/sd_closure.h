@@ -96,8 +96,8 @@ int sd_filter(const double *fine, const int *nel_fine, int ratio, int p, int nv,
  * n_in = n_out = 5 (p+1)^3.  P and Wb stay owned by the caller and are read
  * at each evaluation.  P = NULL switches the closure off.  Inside the
  * solver the network's FP32 sums over K may be taken in another order than
- * in sd_mlp_forward (p = 3 with n_hidden a multiple of 32 up to 256 runs
- * as one launch per RHS), so the two agree to the rounding of those sums,
+ * in sd_mlp_forward (p = 3 with n_hidden = 128 or 256 runs as one launch
+ * per RHS), so the two agree to the rounding of those sums,
  * which can move the BF16 rounding of an activation. */
 int sd_closure_set(sd_ctx *ctx, const sd_mlp_shape *shape, const float *P, const uint16_t *Wb,
                    const float *in_shift, const float *in_scale, const float *out_scale, float max_ratio);
