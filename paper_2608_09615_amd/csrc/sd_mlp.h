@@ -50,11 +50,30 @@ __global__ void __launch_bounds__(256) k_dense_fwd(const uint16_t *__restrict__ 
   const int r = lane & 15, kq = lane >> 4;
   const int row = mt * 16 + r, col = nt * 16 + r;
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4_t a = {0, 0, 0, 0};
-    if (row < M) a = *reinterpret_cast<const bf16x4_t *>(X + (long long)row * K + k0 + 4 * kq);
-    bf16x4_t b = *reinterpret_cast<const bf16x4_t *>(W + (long long)col * K + k0 + 4 * kq);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  // chunks of KU steps: all operand reads of a chunk are issued before its
+  // matrix instructions, from clamped addresses (rows past M read row M - 1
+  // and steps past K the last step, replaced by zeros, so that they add
+  // exact zeros); the products keep the order of k
+  constexpr int KU = 10;
+  const int rowc = row < M ? row : M - 1;
+  const bf16x4_t zero = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += 16 * KU) {
+    bf16x4_t a[KU], b[KU];
+#pragma unroll
+    for (int s = 0; s < KU; ++s) {
+      const int k = min(k0 + 16 * s, K - 16);
+      a[s] = *reinterpret_cast<const bf16x4_t *>(X + (long long)rowc * K + k + 4 * kq);
+      b[s] = *reinterpret_cast<const bf16x4_t *>(W + (long long)col * K + k + 4 * kq);
+    }
+    // keeps the compiler from moving the reads down to their uses
+    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int s = 0; s < KU; ++s) {
+      // the lane's row of X and its column of W are separate operands
+      const bool kin = k0 + 16 * s < K;
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kin && row < M ? a[s] : zero, kin ? b[s] : zero, acc, 0, 0,
+                                                       0);
+    }
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -79,9 +98,9 @@ __global__ void __launch_bounds__(256) k_dense_fwd(const uint16_t *__restrict__ 
 // gradient transposed), summed per lane, then over the four lane groups and
 // the waves in a fixed order.
 template <typename TA>
-__device__ __forceinline__ float ld_as_f32(const TA *p) {
-  if constexpr (sizeof(TA) == 2) return from_bf16(*reinterpret_cast<const uint16_t *>(p));
-  else return *p;
+__device__ __forceinline__ float as_f32(TA v) {
+  if constexpr (sizeof(TA) == 2) return from_bf16((uint16_t)v);
+  else return v;
 }
 
 template <int KW, typename TA, typename TB, bool GELU_BWD>
@@ -99,13 +118,41 @@ __global__ void __launch_bounds__(64 * KW) k_gemm_mfma(int M, int N, int K, cons
   const int kb = w * kc, ke = min(K, kb + kc);
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
   float asum = 0.f;
-#pragma unroll 4
-  for (int k0 = kb; k0 < ke; k0 += 4) {
-    const long long k = k0 + kq;
-    const float a = (m < M && k < ke) ? ld_as_f32(A + m * sam + k * sak) : 0.f;
-    const float b = (n < N && k < ke) ? ld_as_f32(B + k * sbk + n * sbn) : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-    asum += a;
+  // chunks of KU steps: all operand reads of a chunk are issued before its
+  // matrix instructions, from clamped addresses (reads outside the operands
+  // take the last row, column or k and are replaced by zeros, so steps past
+  // the range add exact zeros); the products and sums keep the order of k
+  constexpr int KU = KW >= 8 ? 16 : 10;
+  const long long mc = m < M ? m : M - 1, nc = n < N ? n : N - 1;
+  for (int k0 = kb; k0 < ke; k0 += 4 * KU) {
+    TA a[KU];
+    TB b[KU];
+#pragma unroll
+    for (int s = 0; s < KU; ++s) {
+      const long long k = k0 + 4 * s + kq, kc = k < ke ? k : ke - 1;
+      a[s] = A[mc * sam + kc * sak];
+      b[s] = B[kc * sbk + nc * sbn];
+    }
+    // keeps the compiler from moving the reads down to their uses
+    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int s = 0; s < KU; ++s) {
+      const long long k = k0 + 4 * s + kq;
+      const float av = (m < M && k < ke) ? as_f32(a[s]) : 0.f, bv = (n < N && k < ke) ? as_f32(b[s]) : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      asum += av;
+    }
+  }
+  // the activation's pre-activations, read before the partial tiles are
+  // summed so that their latency passes during the reduction
+  float zv[4] = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (GELU_BWD) {
+    if (w == 0)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long long mo = (long long)blockIdx.y * 16 + 4 * kq + j;
+        zv[j] = Z[(mo < M ? mo : M - 1) * N + nc];
+      }
   }
   if (Bsum && blockIdx.x == 0) {
     // uniform over the block
@@ -129,23 +176,20 @@ __global__ void __launch_bounds__(64 * KW) k_gemm_mfma(int M, int N, int K, cons
     for (int ww = 0; ww < KW - 1; ++ww) v += red[ww][j][lane];
     const long long mo = (long long)blockIdx.y * 16 + 4 * kq + j;
     if (mo < M && n < N) {
-      if constexpr (GELU_BWD) v *= gelu_prime_f(Z[mo * N + n]);
+      if constexpr (GELU_BWD) v *= gelu_prime_f(zv[j]);
       C[mo * N + n] = v;
     }
   }
 }
 
-// dY = 2 w_r (Y - T) / n, one block of 256 lanes per 8 rows (elementwise)
+// dY = 2 w_r (Y - T) / n, one thread per value (elementwise)
 __global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T,
-                                                  const float *__restrict__ w, long long rows, int cols, float scale,
+                                                  const float *__restrict__ w, long long n, int cols, float scale,
                                                   float *__restrict__ dY) {
-  const long long r = (long long)blockIdx.x * 8 + (threadIdx.x >> 5);
-  if (r >= rows) return;
-  const float wr = w ? w[r] : 1.0f;
-  for (int c = threadIdx.x & 31; c < cols; c += 32) {
-    const long long i = r * cols + c;
-    dY[i] = scale * wr * (Y[i] - T[i]);
-  }
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float wr = w ? w[i / cols] : 1.0f;
+  dY[i] = scale * wr * (Y[i] - T[i]);
 }
 
 // loss = sum_r w_r sum_c (Y - T)^2 / n in FP64, one block, a fixed order:
