@@ -116,22 +116,56 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_grad(const double *__res
   if (e >= a.ne) return;
   const int tid = threadIdx.x;
   const R nu = (R)a.nu;
-  for (int t = tid; t < 9 * NL; t += blockDim.x) sS[t] = Sf[e * 9 * NL + t];
-  for (int t = tid; t < NP; t += blockDim.x) {
-    su[t] = cv_in<R>(U[e * NP + t], 0.0);
-    sJ[t] = Jinv[e * NP + t];
+  // the element's metric rows, state and 1/det J and its neighbours' traces:
+  // every read of a lane issued before the first store (clamped indices, so
+  // that no read sits behind a branch)
+  constexpr int NTH = cv_threads<N>();
+  constexpr int IS = (9 * NL + NTH - 1) / NTH, IP = (NP + NTH - 1) / NTH, IF = (6 * NF + NTH - 1) / NTH;
+  R oth[IF];
+  {
+    R vs[IS], vj[IP];
+    double vu[IP];
+#pragma unroll
+    for (int i = 0; i < IS; ++i) vs[i] = Sf[e * 9 * NL + min(tid + i * NTH, 9 * NL - 1)];
+#pragma unroll
+    for (int i = 0; i < IP; ++i) {
+      const int t = min(tid + i * NTH, NP - 1);
+      vu[i] = U[e * NP + t];
+      vj[i] = Jinv[e * NP + t];
+    }
+#pragma unroll
+    for (int i = 0; i < IF; ++i) {
+      const int t = min(tid + i * NTH, 6 * NF - 1);
+      const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
+      oth[i] = T[nbr(a, e, d, s) * 6 * NF + (2 * d + 1 - s) * NF + q];
+    }
+    // keeps the compiler from moving the reads down to their uses
+    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < IS; ++i)
+      if (tid + i * NTH < 9 * NL) sS[tid + i * NTH] = vs[i];
+#pragma unroll
+    for (int i = 0; i < IP; ++i) {
+      const int t = tid + i * NTH;
+      if (t < NP) {
+        su[t] = cv_in<R>(vu[i], 0.0);
+        sJ[t] = vj[i];
+      }
+    }
   }
   __syncthreads();
   // own traces and the common solution at the faces
-  for (int t = tid; t < 6 * NF; t += blockDim.x) {
+#pragma unroll
+  for (int i = 0; i < IF; ++i) {
+    const int t = tid + i * NTH;
+    if (t >= 6 * NF) break;
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
     R v[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) v[c] = su[cv_point<N>(d, q, c)];
     const R own = cv_dot_end<N>(ops, v, s);
-    const R oth = T[nbr(a, e, d, s) * 6 * NF + (2 * d + 1 - s) * NF + q];
     sT[t] = own;
-    sUh[t] = s == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
+    sUh[t] = s == 0 ? R(0.5) * (oth[i] + own) : R(0.5) * (own + oth[i]);
   }
   __syncthreads();
   // continuous solution at the flux points of every family
@@ -228,28 +262,53 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_face(const R *__restrict
   if (e >= a.ne) return;
   const int tid = threadIdx.x;
   const R nu = (R)a.nu;
-  for (int t = tid; t < 6 * NF; t += blockDim.x) {
+  // every read of a lane issued before the first use (clamped indices)
+  constexpr int NTH = cv_threads<N>();
+  constexpr int IF = (6 * NF + NTH - 1) / NTH, IP = (NP + NTH - 1) / NTH;
+  R own[IF], oth[IF], to[IF], tn[IF], pen[IF], part[IP], jin[IP];
+#pragma unroll
+  for (int i = 0; i < IF; ++i) {
+    const int t = min(tid + i * NTH, 6 * NF - 1);
     const int f = t / NF, q = t % NF, d = f >> 1, s = f & 1;
     const long long en = nbr(a, e, d, s);
-    const R own = W[e * 6 * NF + t];
-    const R oth = W[en * 6 * NF + (2 * d + 1 - s) * NF + q];
-    R g = s == 0 ? R(0.5) * (oth + own) : R(0.5) * (own + oth);
+    own[i] = W[e * 6 * NF + t];
+    oth[i] = W[en * 6 * NF + (2 * d + 1 - s) * NF + q];
     if (Pen) {
-      // interior penalty: P' (u_R - u_L), u_R on the +xi_d side
-      const R to = T[e * 6 * NF + t], tn = T[en * 6 * NF + (2 * d + 1 - s) * NF + q];
-      g += Pen[e * 6 * NF + t] * (s == 0 ? to - tn : tn - to);
+      to[i] = T[e * 6 * NF + t];
+      tn[i] = T[en * 6 * NF + (2 * d + 1 - s) * NF + q];
+      pen[i] = Pen[e * 6 * NF + t];
     }
+  }
+#pragma unroll
+  for (int i = 0; i < IP; ++i) {
+    const int pt = min(tid + i * NTH, NP - 1);
+    part[i] = Part[e * NP + pt];
+    jin[i] = Jinv[e * NP + pt];
+  }
+  // keeps the compiler from moving the reads down to their uses
+  __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < IF; ++i) {
+    const int t = tid + i * NTH;
+    if (t >= 6 * NF) break;
+    const int s = (t / NF) & 1;
+    R g = s == 0 ? R(0.5) * (oth[i] + own[i]) : R(0.5) * (own[i] + oth[i]);
+    // interior penalty: P' (u_R - u_L), u_R on the +xi_d side
+    if (Pen) g += pen[i] * (s == 0 ? to[i] - tn[i] : tn[i] - to[i]);
     sGf[t] = -nu * g;
   }
   __syncthreads();
-  for (int pt = tid; pt < NP; pt += blockDim.x) {
-    R acc = Part[e * NP + pt];
+#pragma unroll
+  for (int i = 0; i < IP; ++i) {
+    const int pt = tid + i * NTH;
+    if (pt >= NP) break;
+    R acc = part[i];
     for (int d = 0; d < 3; ++d) {
       int q, c;
       cv_line_of<N>(pt, d, q, c);
       acc += ops[O.M + c * (N + 1)] * sGf[(2 * d) * NF + q] + ops[O.M + c * (N + 1) + N] * sGf[(2 * d + 1) * NF + q];
     }
-    dudt[e * NP + pt] = (double)(-Jinv[e * NP + pt] * acc);
+    dudt[e * NP + pt] = (double)(-jin[i] * acc);
   }
 }
 
@@ -449,18 +508,51 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_grad(const double *__restri
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int t = tid; t < 9 * NL; t += nth) sS[t] = Sf[e * 9 * NL + t];
-  for (int t = tid; t < 5 * NP; t += nth) su[t] = cv_in<R>(U[e * 5 * NP + t], a.U0[t / NP]);
-  for (int t = tid; t < NP; t += nth) sJ[t] = Jinv[e * NP + t];
+  // the element's metric rows, state and 1/det J and its neighbours' traces:
+  // every read of a lane issued before the first store (clamped indices, so
+  // that no read sits behind a branch; kCvnThreads lanes)
+  {
+    constexpr int IS = (9 * NL + kCvnThreads - 1) / kCvnThreads, IU = (5 * NP + kCvnThreads - 1) / kCvnThreads,
+                  IJ = (NP + kCvnThreads - 1) / kCvnThreads, IT = (30 * NF + kCvnThreads - 1) / kCvnThreads;
+    R vs[IS], vj[IJ], vt[IT];
+    double vu[IU];
+#pragma unroll
+    for (int i = 0; i < IS; ++i) vs[i] = Sf[e * 9 * NL + min(tid + i * kCvnThreads, 9 * NL - 1)];
+#pragma unroll
+    for (int i = 0; i < IU; ++i) vu[i] = U[e * 5 * NP + min(tid + i * kCvnThreads, 5 * NP - 1)];
+#pragma unroll
+    for (int i = 0; i < IJ; ++i) vj[i] = Jinv[e * NP + min(tid + i * kCvnThreads, NP - 1)];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = min(tid + i * kCvnThreads, 30 * NF - 1);
+      const int f = t / (5 * NF), w = t % (5 * NF), d = f >> 1, s = f & 1;
+      vt[i] = T[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
+    }
+    // keeps the compiler from moving the reads down to their uses
+    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < IS; ++i)
+      if (tid + i * kCvnThreads < 9 * NL) sS[tid + i * kCvnThreads] = vs[i];
+#pragma unroll
+    for (int i = 0; i < IU; ++i) {
+      const int t = tid + i * kCvnThreads;
+      if (t < 5 * NP) su[t] = cv_in<R>(vu[i], a.U0[t / NP]);
+    }
+#pragma unroll
+    for (int i = 0; i < IJ; ++i)
+      if (tid + i * kCvnThreads < NP) sJ[tid + i * kCvnThreads] = vj[i];
+#pragma unroll
+    for (int i = 0; i < IT; ++i)
+      if (tid + i * kCvnThreads < 30 * NF) sTn[tid + i * kCvnThreads] = vt[i];
+  }
   __syncthreads();
-  // own traces (from the state) and the neighbours'
+  // own traces (from the state)
   for (int t = tid; t < 30 * NF; t += nth) {
     const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF, d = f >> 1, s = f & 1;
     R x[N];
 #pragma unroll
     for (int cc = 0; cc < N; ++cc) x[cc] = su[v * NP + cv_point<N>(d, q, cc)];
     sT[t] = cv_dot_end<N>(ops, x, s);
-    sTn[t] = T[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
   }
   __syncthreads();
   // continuous solution of every variable at the flux points of every family
@@ -573,25 +665,48 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_face(const R *__restrict__ 
   __shared__ R sGf[30 * NF];
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  for (int t = tid; t < 30 * NF; t += nth) {
+  const int tid = threadIdx.x;
+  // every read of a lane issued before the first use (clamped indices)
+  constexpr int IF = (30 * NF + kCvnThreads - 1) / kCvnThreads, IP = (5 * NP + kCvnThreads - 1) / kCvnThreads;
+  R own[IF], oth[IF], part[IP], jin[IP], p0[IP];
+#pragma unroll
+  for (int i = 0; i < IF; ++i) {
+    const int t = min(tid + i * kCvnThreads, 30 * NF - 1);
     const int f = t / (5 * NF), w = t % (5 * NF), d = f >> 1, s = f & 1;
-    const R own = X[e * 30 * NF + t];
-    const R oth = X[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
-    sGf[t] = s == 0 ? oth + own : own + oth;
+    own[i] = X[e * 30 * NF + t];
+    oth[i] = X[nbr(a, e, d, s) * 30 * NF + (2 * d + 1 - s) * 5 * NF + w];
+  }
+#pragma unroll
+  for (int i = 0; i < IP; ++i) {
+    const int t = min(tid + i * kCvnThreads, 5 * NP - 1), v = t / NP, pt = t % NP;
+    part[i] = Part[e * 5 * NP + t];
+    jin[i] = Jinv[e * NP + pt];
+    if (P0div) p0[i] = P0div[(e * 3 + min(max(v - 1, 0), 2)) * NP + pt];
+  }
+  // keeps the compiler from moving the reads down to their uses
+  __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < IF; ++i) {
+    const int t = tid + i * kCvnThreads;
+    if (t >= 30 * NF) break;
+    const int s = (t / (5 * NF)) & 1;
+    sGf[t] = s == 0 ? oth[i] + own[i] : own[i] + oth[i];
   }
   __syncthreads();
-  for (int t = tid; t < 5 * NP; t += nth) {
+#pragma unroll
+  for (int i = 0; i < IP; ++i) {
+    const int t = tid + i * kCvnThreads;
+    if (t >= 5 * NP) break;
     const int v = t / NP, pt = t % NP;
-    R acc = Part[e * 5 * NP + t];
+    R acc = part[i];
     for (int d = 0; d < 3; ++d) {
       int q, cc;
       cv_line_of<N>(pt, d, q, cc);
       acc += ops[O.M + cc * (N + 1)] * sGf[((2 * d) * 5 + v) * NF + q] +
              ops[O.M + cc * (N + 1) + N] * sGf[((2 * d + 1) * 5 + v) * NF + q];
     }
-    double r = (double)(-Jinv[e * NP + pt] * acc);
-    if (P0div && v >= 1 && v <= 3) r += (double)P0div[(e * 3 + v - 1) * NP + pt];
+    double r = (double)(-jin[i] * acc);
+    if (P0div && v >= 1 && v <= 3) r += (double)p0[i];
     dudt[e * 5 * NP + t] = r;
   }
 }
