@@ -679,7 +679,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the right-hand side is "
-              "not sharded across GPUs in this build.", file=sys.stderr)
+              "not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2608_09615_amd import workloads as W
