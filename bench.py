@@ -351,7 +351,8 @@ def oned_bench(torch, args, p=3, N=16):
     elements, p = 3, u0 = sin x, RK4 with dt = 1 / ceil(1 / (0.05 h^2 /
     (p+1)^2)) to t = 1, both schemes, FP64) on the GPU and with the oracle
     on one host thread, and the error against exp(-t) sin x.  The case is
-    64 solution points: the GPU run is bound by its launches."""
+    64 solution points: run step by step, the GPU run is bound by its
+    launches; sd_rk_run takes the whole run in one launch of one block."""
     import numpy as np
     from oracle import oracle as O
     from paper_2608_09615_amd import SD
@@ -386,12 +387,23 @@ def oned_bench(torch, args, p=3, N=16):
         torch.cuda.synchronize()
         tgg = time.perf_counter() - t0
         ugg = u.cpu().numpy()[:, 0, :]
+        # the whole run in one launch (sd_rk_run), after one warm-up run
+        u.copy_(torch.from_numpy(np.ascontiguousarray(u0[:, None, :])))
+        sd.rk_run(u, dt, nst)
+        u.copy_(torch.from_numpy(np.ascontiguousarray(u0[:, None, :])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sd.rk_run(u, dt, nst)
+        torch.cuda.synchronize()
+        tgr = time.perf_counter() - t0
+        ugr = u.cpu().numpy()[:, 0, :]
         sd.close()
         t0 = time.perf_counter()
         uo = O.rk4_1d(u0, p, 0.0, 2 * math.pi, dt, nst, scheme=scheme)
         to = time.perf_counter() - t0
         ex = math.exp(-1.0) * np.sin(x)
         out[scheme] = {"gpu_s": tg, "gpu_graph_s": tgg, "graph_vs_eager": float(np.abs(ugg - ug).max()),
+                       "gpu_one_launch_s": tgr, "one_launch_vs_eager": float(np.abs(ugr - ug).max()),
                        "oracle_1thread_s": to, "gpu_max_err": float(np.abs(ug - ex).max()),
                        "oracle_max_err": float(np.abs(uo - ex).max()),
                        "gpu_vs_oracle": float(np.abs(ug - uo).max())}

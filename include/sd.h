@@ -155,6 +155,19 @@ int sd_rhs(sd_ctx *ctx, const double *u, double *dudt);
  * values the RHS would round them to). */
 int sd_rk_step(sd_ctx *ctx, double *u, double dt);
 
+/* nsteps time steps of size dt, in place on the device state u: the state
+ * of nsteps calls of sd_rk_step (to the last bit of a value, where the
+ * compiler fuses a product and a sum differently in the one-launch kernel
+ * and the separate ones).  A one-dimensional FP64
+ * problem of linear diffusion or the porous medium equation (section 3)
+ * with classical RK4, n = p + 1 <= 8 and at most 2048 solution points runs
+ * the whole run in one launch of one block, the mesh held in on-chip memory
+ * (such meshes give the separate kernels of a step too little work to be
+ * anything but launch bound); every other context takes the steps one by
+ * one.  nsteps < 0 or a non-finite dt: SD_EINVAL; nsteps = 0 does nothing.
+ * The one-launch run records no sd_timing events. */
+int sd_rk_run(sd_ctx *ctx, double *u, double dt, long long nsteps);
+
 /* Diagnostics of a Navier-Stokes state (FP64 reductions, deterministic):
  * waits for the stream and fills the host struct *out.  Returns
  * SD_ENONFINITE (with *out filled) when the state holds NaN or Inf. */

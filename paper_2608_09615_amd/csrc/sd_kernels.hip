@@ -505,4 +505,5 @@ __global__ void k_diag_final(const double *__restrict__ part, int nparts, double
 #include "sd_dispatch.inc"
 #include "sd_closure.inc"
 #include "sd_bloch.inc"
+#include "sd_run1d.inc"
 #include "sd_curv.inc"

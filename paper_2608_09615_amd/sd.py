@@ -17,7 +17,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32mfma": 3}
 INTEGRATORS = {"rk4": 0, "ssprk54": 1}
 
 EXPORTS = ["sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_state_size", "sd_rhs",
-           "sd_rk_step", "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
+           "sd_rk_step", "sd_rk_run", "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
            "sd_last_error",
            "sd_mlp_param_count", "sd_mlp_work_bytes", "sd_mlp_round_weights", "sd_mlp_forward",
            "sd_mlp_forward_noalloc",
@@ -94,6 +94,7 @@ def load_library(path=LIB_PATH):
     L.sd_state_size.restype = ctypes.c_longlong
     L.sd_rhs.argtypes = [vp, vp, vp]
     L.sd_rk_step.argtypes = [vp, vp, ctypes.c_double]
+    L.sd_rk_run.argtypes = [vp, vp, ctypes.c_double, ctypes.c_longlong]
     L.sd_diagnostics.argtypes = [vp, vp, ctypes.POINTER(Diag)]
     L.sd_stable_dt.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.sd_set_geometry.argtypes = [vp, vp, ctypes.c_int]
@@ -118,7 +119,7 @@ def load_library(path=LIB_PATH):
     L.sd_bloch.argtypes = [ctypes.POINTER(BlochCfg), vp, ctypes.c_longlong, vp, ctypes.c_int, vp, vp, vp, vp, vp]
     L.sd_last_error.argtypes = []
     L.sd_last_error.restype = ctypes.c_char_p
-    for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step",
+    for f in ("sd_params_default", "sd_init", "sd_free", "sd_set_stream", "sd_rhs", "sd_rk_step", "sd_rk_run",
               "sd_diagnostics", "sd_stable_dt", "sd_set_geometry", "sd_timing", "sd_timing_read",
               "sd_mlp_round_weights",
               "sd_mlp_forward", "sd_mlp_forward_noalloc",
@@ -207,6 +208,16 @@ class SD:
         self._check_state(u)
         self._stream()
         _check(load_library().sd_rk_step(self._ctx, ctypes.c_void_p(u.data_ptr()), float(dt)))
+        return u
+
+    def rk_run(self, u, dt, nsteps):
+        """``nsteps`` steps of size ``dt`` on ``u`` in place (sd_rk_run: one
+        launch for the whole run of a small one-dimensional FP64 problem,
+        otherwise the steps one by one; the same state either way, to the
+        last bit of a value)."""
+        self._check_state(u)
+        self._stream()
+        _check(load_library().sd_rk_run(self._ctx, ctypes.c_void_p(u.data_ptr()), float(dt), int(nsteps)))
         return u
 
     def rk_steps(self, u, dt, nsteps, graph_steps=0):
