@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libsd.so")
 
 SOURCES = ["sd_kernels.hip", "sd_operators.cpp"]
 HEADERS = ["sd_internal.h", "sd_physics.h", "sd_ns_kernel.h", "sd_mlp.h", "sd_bloch_kernel.h", "sd_curv_kernel.h",
-           "sd_dispatch.inc", "sd_closure.inc", "sd_bloch.inc", "sd_curv.inc"]
+           "sd_dispatch.inc", "sd_closure.inc", "sd_bloch.inc", "sd_curv.inc", "sd_run1d.inc"]
 
 # Packed FP32 instructions stay off: the compiler must not form them.
 HIPCC_FLAGS = [
