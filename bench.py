@@ -75,7 +75,7 @@ def parse():
                     help="precision of the --only curvilinear workloads")
     ap.add_argument("--closure-nel", type=int, default=16,
                     help="elements per direction of the learned-closure timing (0: skip it)")
-    ap.add_argument("--only", choices=["bloch", "curvilinear", "curvilinear_ns", "closure", "training"],
+    ap.add_argument("--only", choices=["bloch", "curvilinear", "curvilinear_ns", "closure", "training", "oned"],
                     default=None,
                     help="time only that workload and print its record")
     return ap.parse_args()
@@ -720,6 +720,9 @@ def main():
         return
     if args.only == "training":
         print(json.dumps({"closure_training": training_bench(torch, args)}), flush=True)
+        return
+    if args.only == "oned":
+        print(json.dumps({"oned_whole_run": oned_bench(torch, args)}), flush=True)
         return
     nel = (args.nel,) * 3
     U0 = W.tgv_state(nel, args.p)
