@@ -91,12 +91,26 @@ __global__ void __launch_bounds__(cv_threads<N>()) k_cv_traces(const double *__r
   const long long e = blockIdx.x;
   if (e >= ne) return;
   const double *u = U + e * NP;
-  for (int t = threadIdx.x; t < 6 * NF; t += blockDim.x) {
-    const int f = t / NF, q = t % NF, d = f >> 1;
+  // every read of a lane issued before the first trace (clamped indices)
+  constexpr int NTH = cv_threads<N>(), IT = (6 * NF + NTH - 1) / NTH;
+  const int tid = threadIdx.x;
+  double x[IT][N];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = min(tid + i * NTH, 6 * NF - 1), f = t / NF, q = t % NF, d = f >> 1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[i][c] = u[cv_point<N>(d, q, c)];
+  }
+  // keeps the compiler from moving the reads down to their uses
+  __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = tid + i * NTH;
+    if (t >= 6 * NF) break;
     R v[N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = cv_in<R>(u[cv_point<N>(d, q, c)], 0.0);
-    T[e * 6 * NF + t] = cv_dot_end<N>(ops, v, f & 1);
+    for (int c = 0; c < N; ++c) v[c] = cv_in<R>(x[i][c], 0.0);
+    T[e * 6 * NF + t] = cv_dot_end<N>(ops, v, (t / NF) & 1);
   }
 }
 
@@ -452,12 +466,28 @@ __global__ void __launch_bounds__(kCvnThreads) k_cvn_traces(const double *__rest
   constexpr int NP = N * N * N, NF = N * N;
   const long long e = blockIdx.x;
   if (e >= a.ne) return;
-  for (int t = threadIdx.x; t < 30 * NF; t += blockDim.x) {
+  // every read of a lane issued before the first trace (clamped indices)
+  constexpr int IT = (30 * NF + kCvnThreads - 1) / kCvnThreads;
+  const int tid = threadIdx.x;
+  double y[IT][N];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = min(tid + i * kCvnThreads, 30 * NF - 1);
     const int f = t / (5 * NF), w = t % (5 * NF), v = w / NF, q = w % NF, d = f >> 1;
     const double *u = U + (e * 5 + v) * NP;
+#pragma unroll
+    for (int c = 0; c < N; ++c) y[i][c] = u[cv_point<N>(d, q, c)];
+  }
+  // keeps the compiler from moving the reads down to their uses
+  __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = tid + i * kCvnThreads;
+    if (t >= 30 * NF) break;
+    const int f = t / (5 * NF), v = (t % (5 * NF)) / NF;
     R x[N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) x[c] = cv_in<R>(u[cv_point<N>(d, q, c)], a.U0[v]);
+    for (int c = 0; c < N; ++c) x[c] = cv_in<R>(y[i][c], a.U0[v]);
     T[e * 30 * NF + t] = cv_dot_end<N>(ops, x, f & 1);
   }
 }
