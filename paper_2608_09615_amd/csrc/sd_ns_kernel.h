@@ -925,10 +925,10 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
   const int nb = min(epb, (int)(a.ne - e0));
   const R *__restrict__ in_r = ch.in_r;
 
-  // FP64 (two wavefronts per SIMD): the waves of blocks in the prologue, the
-  // phase that reads the neighbours' states, issue ahead of those computing
-  // (32^3 p = 3: 504 -> 478 us per stage; FP32 unchanged, so left out)
-  if constexpr (sizeof(R) == 8) __builtin_amdgcn_s_setprio(2);
+  // the waves of blocks in the prologue, the phase that reads the
+  // neighbours' states, issue ahead of those computing (32^3 p = 3: FP64
+  // 504 -> 479 us per stage, FP32 204 -> 199 us)
+  __builtin_amdgcn_s_setprio(3);
   // P0: neighbour table; then the state and the neighbours' traces computed
   // from their states (read through L2)
   for (int t = tid; t < nb * NNB; t += nth) snb[t / NNB][t % NNB] = ns_neighbour(a, e0 + t / NNB, t % NNB);
@@ -950,7 +950,7 @@ __attribute__((amdgpu_waves_per_eu(ns_waves_per_simd<N, R>(), 8))) k_rhs_ns(cons
     else ns_prologue<N, R, COMPACT, NNB>(NsSrcU<R>{U, a.U0[0], a.U0[4]}, to, sm, snb, e0, nb, tid);
   }
   __syncthreads();
-  if constexpr (sizeof(R) == 8) __builtin_amdgcn_s_setprio(0);
+  __builtin_amdgcn_s_setprio(0);
   // P2: gradient at the solution points
   if constexpr (SPLIT) {
     // one column per (direction, element, variable, line):
